@@ -1,0 +1,206 @@
+/*
+ * sptrsv.h -- C ABI of a level-scheduled sparse lower-triangular solver for
+ * AMD Instinct MI355X (gfx950) with host-side equation rewriting.
+ *
+ * Method: Yilmaz, "Graph Transformation and Specialized Code Generation for
+ * Sparse Triangular Solve (SpTRSV)", arXiv:2103.11445.
+ *   - the solve of L x = b by forward substitution over CSR and the
+ *     dependency DAG of L, grouped into levels: Sec. II (Algorithm 1, Fig. 1);
+ *   - equation rewriting of rows in thin levels, which moves them to earlier
+ *     levels and removes synchronisation points: Sec. III (Fig. 2, Fig. 3);
+ *   - matrix analysis (rows, nonzeros, DAG, level sets, per-level
+ *     statistics) feeding the rewrite: Sec. IV.
+ *
+ * Conventions shared by every entry point:
+ *   - Nothing throws across this boundary; each call returns a status code
+ *     and, on failure, leaves a message readable with sptrsv_last_error().
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device allocations on the GPU that is current when the call is made.
+ *   - Streams are hipStream_t passed as void* (NULL = the null stream).
+ *   - L is n x n lower triangular in CSR with int32 indices and FP64 values:
+ *     row_ptr[0] = 0, row_ptr non-decreasing, within each row the columns
+ *     strictly increase and the last entry is the diagonal (non-zero).
+ *   - A plan is not thread-safe: calls on one plan must not overlap, and two
+ *     solves of one plan must not run concurrently on different streams
+ *     (they share the plan's device workspace).  Distinct plans are
+ *     independent.
+ */
+#ifndef SPTRSV_H
+#define SPTRSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque plan.  Owned by the library; release with sptrsv_plan_destroy. */
+typedef struct sptrsv_plan_s *sptrsv_plan;
+
+typedef enum {
+    SPTRSV_OK = 0,
+    SPTRSV_ERR_ARG = 1,      /* null pointer, negative size, invalid policy field,
+                                b aliasing x, buffer too small */
+    SPTRSV_ERR_CSR = 2,      /* row_ptr[0] != 0 or decreasing, empty row, column
+                                out of range, columns not strictly increasing,
+                                entry above the diagonal */
+    SPTRSV_ERR_DIAG = 3,     /* a row whose last entry is not its diagonal, or a
+                                zero diagonal */
+    SPTRSV_ERR_OVERFLOW = 4, /* the rewritten system does not fit int32 device
+                                indexing */
+    SPTRSV_ERR_OOM = 5,      /* host allocation failed */
+    SPTRSV_ERR_HIP = 6,      /* a HIP runtime call failed (message has details) */
+    SPTRSV_ERR_STATE = 7,    /* solve before upload, or after a rewrite made the
+                                uploaded image stale */
+    SPTRSV_ERR_TIMEOUT = 8   /* reported by sptrsv_check: a dependency wait in
+                                the kernel gave up (the solution is invalid) */
+} sptrsv_status;
+
+/* Which levels to rewrite (Sec. III: rows of thin levels are moved into an
+ * earlier level by substituting the equations of their dependencies; the
+ * paper chooses them by hand, Sec. IV and V).
+ *
+ * Levels are cut into consecutive stages.  A stage keeps its first level a;
+ * every row of a later level l of the stage has its dependencies of level
+ * >= a substituted away (original equations, latest dependency first, equal
+ * x terms merged: Fig. 2 and Fig. 3), so after rewriting it depends only on
+ * rows of earlier stages.  Level 0 always opens stage 0.  Level l >= 1 joins
+ * the current stage when:
+ *   SPTRSV_POLICY_NONE       never (plain level-set schedule);
+ *   SPTRSV_POLICY_THRESHOLD  width(l) <= max_width, the stage holds fewer than
+ *                            max_depth levels, the entries added by all
+ *                            absorbed levels stay <= floor(max_fill * nnz(L)),
+ *                            and nnz(L') + nnz(M) stays <= max_entries;
+ *   SPTRSV_POLICY_EXPLICIT   absorb[l] != 0 (l < absorb_len) and
+ *                            nnz(L') + nnz(M) stays <= max_entries.
+ * Entries added by absorbing l: over its rows, (x-terms + b-terms after
+ * rewriting) - (off-diagonals before), counted symbolically. */
+enum {
+    SPTRSV_POLICY_NONE = 0,
+    SPTRSV_POLICY_THRESHOLD = 1,
+    SPTRSV_POLICY_EXPLICIT = 2
+};
+
+typedef struct {
+    int32_t kind;           /* SPTRSV_POLICY_* */
+    int32_t max_width;      /* >= 0; a level is thin if it has <= max_width rows */
+    int32_t max_depth;      /* >= 1; levels per stage, including its first */
+    double max_fill;        /* >= 0; added entries budget as a multiple of nnz(L) */
+    int64_t max_entries;    /* >= 0; cap on nnz(L') + nnz(M) */
+    const uint8_t *absorb;  /* host, absorb_len bytes; EXPLICIT only (may be NULL
+                               when absorb_len == 0); read during the call only */
+    int32_t absorb_len;     /* >= 0 */
+} sptrsv_policy;
+
+/* Fills *p with THRESHOLD, max_width 4, max_depth 64, max_fill 0.25,
+ * max_entries INT32_MAX, no mask. */
+void sptrsv_policy_default(sptrsv_policy *p);
+
+/* Matrix analysis (Sec. IV; DAG and level sets of Sec. II).  Validates and
+ * copies L (host arrays, read during the call only; the caller keeps
+ * ownership), builds the level of every row (0 for rows without
+ * off-diagonals, else 1 + the deepest dependency) and the level sets.  The
+ * new plan carries the plain schedule (as after SPTRSV_POLICY_NONE).
+ * n == 0 gives an empty plan whose solve does nothing.  On error *out is
+ * set to NULL.  Errors: ARG (n < 0, null pointer with n > 0 or out NULL),
+ * CSR, DIAG, OOM. */
+sptrsv_status sptrsv_analyse(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             const double *val, sptrsv_plan *out);
+
+/* Equation rewriting (Sec. III) under *policy, always starting again from
+ * the analysed L (so repeated calls do not compound).  Builds the rewritten
+ * rows L' (x-terms plus the unchanged diagonal), the right-hand-side
+ * combination M (b'_i = b_i + sum_j M_ij b_j), re-levels L' (emptied levels
+ * vanish) and packs the device image.  Host only; invalidates a previous
+ * upload.  Errors: ARG (bad policy), OVERFLOW (the device image would need
+ * more than INT32_MAX 64-lane chunks or entries), OOM. */
+sptrsv_status sptrsv_rewrite(sptrsv_plan plan, const sptrsv_policy *policy);
+
+/* Size in bytes of the device buffer the current plan needs (image plus
+ * workspace). */
+sptrsv_status sptrsv_device_bytes(sptrsv_plan plan, size_t *bytes);
+
+/* Copies the packed plan into dev_buf (device, >= sptrsv_device_bytes, owned
+ * by the caller, 256-byte aligned, must stay allocated while the plan is
+ * solved with) on stream, and waits for the copy to finish.  The plan
+ * remembers dev_buf.  Errors: ARG (null, too small, misaligned), HIP. */
+sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void *stream);
+
+/* Solves L x = b (device arrays of n doubles, b != x, neither overlapping
+ * the plan buffer) with the uploaded schedule: enqueues one fill of x and one
+ * solve kernel on stream and returns without waiting.  Every row waits only
+ * for the rows it still depends on (per-row readiness, in level order), so
+ * the level structure bounds the critical path.  Numerical problems are not
+ * reported (zero diagonals were rejected by analyse); a dependency wait
+ * that exceeds the wait limit is reported by sptrsv_check.  Errors: ARG,
+ * STATE (not uploaded or stale), HIP. */
+sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *stream);
+
+/* Waits for stream, then reads and clears the plan's device status word:
+ * *device_status = 0 if every solve since the last check completed normally,
+ * else SPTRSV_ERR_TIMEOUT.  Errors: ARG, STATE, HIP. */
+sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_status);
+
+/* Upper bound, in ticks of the 100 MHz GPU real-time clock, on a single
+ * dependency wait (default 200,000,000 = 2 s).  A wait that reaches it
+ * gives up, marks the plan's status word and lets the kernel drain.
+ * For tests of the failure path.  Takes effect at the next solve. */
+sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks);
+
+/* Plan statistics (Sec. V reports levels and FLOPs before and after).
+ * flops: 2 per stored off-diagonal x-term or b-term plus 1 per row.
+ * bytes: compulsory traffic of one solve, 12 per stored entry (int32 column +
+ * FP64 value, diagonals included) + 24 per row (row offset, row id, b_i,
+ * x_i); gathers of x and b are counted as cache hits. */
+typedef struct {
+    int32_t n;
+    int32_t levels;      /* levels of L */
+    int32_t stages;      /* stages chosen by the rewrite */
+    int32_t levels_rw;   /* levels of L' (the executed schedule) */
+    int64_t nnz;         /* nnz(L), diagonals included */
+    int64_t nnz_rw;      /* nnz(L'), diagonals included */
+    int64_t nnz_m;       /* nnz(M) */
+    int64_t flops;       /* of the plain solve */
+    int64_t flops_rw;    /* of the rewritten solve */
+    int64_t bytes;       /* of the plain solve */
+    int64_t bytes_rw;    /* of the rewritten solve */
+    int64_t device_bytes;/* size of the device image + workspace */
+    int64_t tiles;       /* 64-lane work tiles in the device schedule */
+} sptrsv_info;
+sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
+
+/* Level of every row (host int32[n]): which = 0 for L, 1 for L'. */
+sptrsv_status sptrsv_plan_levels(sptrsv_plan plan, int32_t which, int32_t *level);
+
+/* Stage of every level of L (host int32[levels]) and the entries each
+ * absorbed level added (host int64[levels], 0 for levels that open a stage);
+ * either pointer may be NULL. */
+sptrsv_status sptrsv_plan_stages(sptrsv_plan plan, int32_t *stage_of_level,
+                                 int64_t *delta_of_level);
+
+/* The executed schedule: level sets of L' (host int32[levels_rw + 1] and
+ * int32[n]; rows ascending within a level). */
+sptrsv_status sptrsv_plan_schedule(sptrsv_plan plan, int32_t *level_ptr, int32_t *rows);
+
+/* The rewritten system as CSR (host arrays sized by sptrsv_plan_info):
+ * L' = (lp_ptr int64[n+1], lp_col int32[nnz_rw], lp_val double[nnz_rw]) with
+ * ascending columns and the diagonal last, and M = (m_ptr int64[n+1],
+ * m_col int32[nnz_m], m_val double[nnz_m]) with ascending columns. */
+sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_col,
+                                 double *lp_val, int64_t *m_ptr, int32_t *m_col,
+                                 double *m_val);
+
+/* Releases the plan (host memory only; the caller frees its device buffer
+ * after the last solve that uses it has finished).  NULL is ignored. */
+void sptrsv_plan_destroy(sptrsv_plan plan);
+
+/* Message of the last failed call on this thread ("" if none); valid until
+ * the next call on this thread. */
+const char *sptrsv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPTRSV_H */

@@ -1,0 +1,222 @@
+"""Level-scheduled sparse lower-triangular solve with equation rewriting on
+MI355X (gfx950) -- Python binding of ``libsptrsv.so``.
+
+This module only marshals arguments to the C ABI declared in
+``include/sptrsv.h``: every step of analysis, rewriting and solving runs in
+the library (host passes in C++, the solve in HIP kernels).  PyTorch is used
+for device memory and streams only.  If the library is not built, importing
+works but every call raises :class:`SptrsvError`; there is no fallback.
+
+Method: arXiv:2103.11445 -- forward substitution over the level sets of
+DAG_L (Sec. II) with rows of thin levels rewritten into earlier levels by
+substituting their dependencies' equations (Sec. III).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Plan", "Policy", "SptrsvError", "library_path", "load", "STATUS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
+
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CSR", 3: "ERR_DIAG", 4: "ERR_OVERFLOW",
+          5: "ERR_OOM", 6: "ERR_HIP", 7: "ERR_STATE", 8: "ERR_TIMEOUT"}
+KIND = {"none": 0, "threshold": 1, "explicit": 2}
+INT32_MAX = 2**31 - 1
+
+
+class SptrsvError(RuntimeError):
+    """A library call returned a non-zero status."""
+
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Policy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("max_width", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("max_fill", ctypes.c_double),
+                ("max_entries", ctypes.c_int64), ("absorb", ctypes.c_void_p),
+                ("absorb_len", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("levels", ctypes.c_int32), ("stages", ctypes.c_int32),
+                ("levels_rw", ctypes.c_int32), ("nnz", ctypes.c_int64), ("nnz_rw", ctypes.c_int64),
+                ("nnz_m", ctypes.c_int64), ("flops", ctypes.c_int64), ("flops_rw", ctypes.c_int64),
+                ("bytes", ctypes.c_int64), ("bytes_rw", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load ``libsptrsv.so`` (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise SptrsvError(6, f"{_LIB_PATH} is not built; run python -m paper_2103_11445_amd.build")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    S = ctypes.c_int
+    sig = {
+        "sptrsv_policy_default": (None, [P]),
+        "sptrsv_analyse": (S, [I32, P, P, P, P]),
+        "sptrsv_rewrite": (S, [P, P]),
+        "sptrsv_device_bytes": (S, [P, P]),
+        "sptrsv_upload": (S, [P, P, ctypes.c_size_t, P]),
+        "sptrsv_solve": (S, [P, P, P, P]),
+        "sptrsv_check": (S, [P, P, P]),
+        "sptrsv_set_wait_limit": (S, [P, U64]),
+        "sptrsv_plan_info": (S, [P, P]),
+        "sptrsv_plan_levels": (S, [P, I32, P]),
+        "sptrsv_plan_stages": (S, [P, P, P]),
+        "sptrsv_plan_schedule": (S, [P, P, P]),
+        "sptrsv_plan_export": (S, [P, P, P, P, P, P, P]),
+        "sptrsv_plan_destroy": (None, [P]),
+        "sptrsv_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise SptrsvError(status, load().sptrsv_last_error().decode())
+
+
+def _ptr(a) -> ctypes.c_void_p:
+    if a is None:
+        return ctypes.c_void_p(0)
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())  # torch tensor
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_policy(kind: str = "threshold", max_width: int = 4, max_depth: int = 64,
+                max_fill: float = 0.25, max_entries: int = INT32_MAX, absorb=None):
+    """A :class:`Policy` (and the mask array that must outlive the call)."""
+    mask = None
+    if absorb is not None:
+        mask = np.ascontiguousarray(absorb, dtype=np.uint8)
+    pol = Policy(KIND[kind], int(max_width), int(max_depth), float(max_fill), int(max_entries),
+                 None if mask is None else mask.ctypes.data, 0 if mask is None else mask.size)
+    return pol, mask
+
+
+class Plan:
+    """Analysis, rewrite and solve of one lower-triangular CSR matrix."""
+
+    def __init__(self, row_ptr, col_idx, val):
+        lib = load()
+        self._rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        n = self._rp.size - 1
+        h = ctypes.c_void_p()
+        _check(lib.sptrsv_analyse(n, _ptr(self._rp), _ptr(ci), _ptr(v), ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self._buf = None
+
+    # ---------------------------------------------------------- host side --
+    def rewrite(self, kind: str = "threshold", **kw) -> "Plan":
+        pol, mask = make_policy(kind, **kw)
+        _check(load().sptrsv_rewrite(self._h, ctypes.byref(pol)))
+        del mask
+        return self
+
+    def info(self) -> dict:
+        o = _Info()
+        _check(load().sptrsv_plan_info(self._h, ctypes.byref(o)))
+        return {f: getattr(o, f) for f, _ in _Info._fields_}
+
+    def levels(self, which: int = 0) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int32)
+        _check(load().sptrsv_plan_levels(self._h, which, _ptr(out)))
+        return out
+
+    def stages(self):
+        nlev = self.info()["levels"]
+        s = np.empty(max(nlev, 1), dtype=np.int32)
+        d = np.empty(max(nlev, 1), dtype=np.int64)
+        _check(load().sptrsv_plan_stages(self._h, _ptr(s), _ptr(d)))
+        return s[:nlev], d[:nlev]
+
+    def schedule(self):
+        nl = self.info()["levels_rw"]
+        ptr = np.empty(nl + 1, dtype=np.int32)
+        rows = np.empty(self.n, dtype=np.int32)
+        _check(load().sptrsv_plan_schedule(self._h, _ptr(ptr), _ptr(rows)))
+        return ptr, rows
+
+    def export(self):
+        i = self.info()
+        lp = (np.empty(self.n + 1, np.int64), np.empty(i["nnz_rw"], np.int32),
+              np.empty(i["nnz_rw"], np.float64))
+        m = (np.empty(self.n + 1, np.int64), np.empty(i["nnz_m"], np.int32),
+             np.empty(i["nnz_m"], np.float64))
+        _check(load().sptrsv_plan_export(self._h, *(_ptr(a) for a in lp), *(_ptr(a) for a in m)))
+        return lp, m
+
+    def set_wait_limit(self, ticks: int):
+        _check(load().sptrsv_set_wait_limit(self._h, int(ticks)))
+
+    # -------------------------------------------------------- device side --
+    def upload(self, device=None, stream=None) -> "Plan":
+        """Allocate the device buffer with torch and copy the plan into it."""
+        import torch
+        nb = ctypes.c_size_t()
+        _check(load().sptrsv_device_bytes(self._h, ctypes.byref(nb)))
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._buf = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=dev)
+        _check(load().sptrsv_upload(self._h, _ptr(self._buf), self._buf.numel(), _stream(stream)))
+        return self
+
+    def solve(self, b, x=None, stream=None):
+        """Enqueue x = L^-1 b on ``stream`` (default: torch's current stream)
+        and return x (a float64 CUDA tensor)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().sptrsv_solve(self._h, _ptr(b), _ptr(x), _stream(stream)))
+        return x
+
+    def check(self, stream=None) -> int:
+        st = ctypes.c_int32()
+        _check(load().sptrsv_check(self._h, _stream(stream), ctypes.byref(st)))
+        return st.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().sptrsv_plan_destroy(self._h)
+            self._h = None
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,68 @@
+// analyse.cpp -- matrix analysis (arXiv:2103.11445, Sec. IV): validate and
+// copy L, build DAG_L's level of every row and the level sets (Sec. II).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "plan.hpp"
+
+namespace sptrsv {
+
+static void fail(sptrsv_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void validate_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *val) {
+    if (n < 0) fail(SPTRSV_ERR_ARG, "n < 0");
+    if (n == 0) return;
+    if (!rp || !ci || !val) fail(SPTRSV_ERR_ARG, "null CSR array");
+    if (rp[0] != 0) fail(SPTRSV_ERR_CSR, "row_ptr[0] != 0");
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t b = rp[i], e = rp[i + 1];
+        if (e < b) fail(SPTRSV_ERR_CSR, "row_ptr decreases at row " + std::to_string(i));
+        if (e == b) fail(SPTRSV_ERR_DIAG, "row " + std::to_string(i) + " is empty (no diagonal)");
+        int32_t prev = -1;
+        for (int32_t p = b; p < e; ++p) {
+            const int32_t c = ci[p];
+            if (c < 0 || c >= n) fail(SPTRSV_ERR_CSR, "column out of range in row " + std::to_string(i));
+            if (c <= prev) fail(SPTRSV_ERR_CSR, "columns not strictly increasing in row " + std::to_string(i));
+            if (c > i) fail(SPTRSV_ERR_CSR, "entry above the diagonal in row " + std::to_string(i));
+            prev = c;
+        }
+        if (ci[e - 1] != i) fail(SPTRSV_ERR_DIAG, "row " + std::to_string(i) + " has no diagonal");
+        if (val[e - 1] == 0.0) fail(SPTRSV_ERR_DIAG, "zero diagonal in row " + std::to_string(i));
+    }
+}
+
+void level_sets(int32_t n, const int32_t *level, int32_t nlev, std::vector<int32_t> &ptr,
+                std::vector<int32_t> &rows) {
+    ptr.assign((size_t)nlev + 1, 0);
+    rows.resize((size_t)n);
+    for (int32_t i = 0; i < n; ++i) ++ptr[(size_t)level[i] + 1];
+    for (int32_t l = 0; l < nlev; ++l) ptr[(size_t)l + 1] += ptr[(size_t)l];
+    std::vector<int32_t> cur(ptr.begin(), ptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i) rows[(size_t)cur[(size_t)level[i]]++] = i;
+}
+
+void analyse(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const double *val) {
+    validate_csr(n, rp, ci, val);
+    p.n = n;
+    const size_t nnz = n ? (size_t)rp[n] : 0;
+    p.rp.assign(rp, rp + (size_t)n + 1 - (n == 0));
+    if (n == 0) p.rp.assign(1, 0);
+    p.ci.assign(ci, ci + nnz);
+    p.val.assign(val, val + nnz);
+    // Level of a row: one more than the deepest row it depends on; rows
+    // depend only on earlier rows, so one pass in row order suffices.
+    p.level.resize((size_t)n);
+    int32_t maxlev = -1;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t lv = 0;
+        for (int32_t q = rp[i]; q < rp[i + 1] - 1; ++q) lv = std::max(lv, p.level[(size_t)ci[q]] + 1);
+        p.level[(size_t)i] = lv;
+        maxlev = std::max(maxlev, lv);
+    }
+    p.nlev = maxlev + 1;
+    level_sets(n, p.level.data(), p.nlev, p.level_ptr, p.level_rows);
+}
+
+}  // namespace sptrsv

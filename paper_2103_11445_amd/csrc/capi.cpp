@@ -1,0 +1,243 @@
+// capi.cpp -- the extern "C" boundary declared in include/sptrsv.h.
+// Turns internal errors into status codes plus a thread-local message, and
+// moves plans between host and device.
+#include <hip/hip_runtime_api.h>
+
+#include <climits>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <algorithm>
+#include <cstddef>
+#include <string>
+
+#include "plan.hpp"
+
+struct sptrsv_plan_s : sptrsv::Plan {};
+
+namespace {
+thread_local std::string g_err;
+
+sptrsv_status set_err(sptrsv_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+template <class F>
+sptrsv_status guarded(F &&f) {
+    try {
+        g_err.clear();
+        return f();
+    } catch (const sptrsv::Error &e) {
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SPTRSV_ERR_OOM, "out of host memory");
+    } catch (const std::length_error &) {
+        return set_err(SPTRSV_ERR_OOM, "out of host memory");
+    }
+}
+
+sptrsv_status hip_err(hipError_t e, const char *what) {
+    return set_err(SPTRSV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + bn && pb < pa + an;
+}
+}  // namespace
+
+extern "C" {
+
+void sptrsv_policy_default(sptrsv_policy *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->kind = SPTRSV_POLICY_THRESHOLD;
+    p->max_width = 4;
+    p->max_depth = 64;
+    p->max_fill = 0.25;
+    p->max_entries = INT32_MAX;
+}
+
+sptrsv_status sptrsv_analyse(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             const double *val, sptrsv_plan *out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> sptrsv_status {
+        if (!out) return set_err(SPTRSV_ERR_ARG, "out is NULL");
+        sptrsv_plan p = new sptrsv_plan_s();
+        try {
+            sptrsv::analyse(*p, n, row_ptr, col_idx, val);
+            sptrsv_policy none{};
+            none.kind = SPTRSV_POLICY_NONE;
+            sptrsv::rewrite(*p, none);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_rewrite(sptrsv_plan plan, const sptrsv_policy *policy) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan || !policy) return set_err(SPTRSV_ERR_ARG, "null argument");
+        sptrsv::validate_policy(*policy);
+        plan->uploaded = false;
+        try {
+            sptrsv::rewrite(*plan, *policy);
+        } catch (...) {
+            // leave a consistent plan behind: the plain schedule
+            sptrsv_policy none{};
+            none.kind = SPTRSV_POLICY_NONE;
+            try {
+                sptrsv::rewrite(*plan, none);
+            } catch (...) {
+            }
+            throw;
+        }
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_device_bytes(sptrsv_plan plan, size_t *bytes) {
+    if (!plan || !bytes) return set_err(SPTRSV_ERR_ARG, "null argument");
+    *bytes = plan->layout.total;
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan || !dev_buf) return set_err(SPTRSV_ERR_ARG, "null argument");
+        if (bytes < plan->layout.total)
+            return set_err(SPTRSV_ERR_ARG, "device buffer smaller than sptrsv_device_bytes");
+        if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0)
+            return set_err(SPTRSV_ERR_ARG, "device buffer not 256-byte aligned");
+        int waves = 0;
+        if (int e = sptrsv_device_waves(&waves)) return hip_err((hipError_t)e, "device query");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        hipError_t e = hipMemcpyAsync(dev_buf, plan->image.data(), plan->layout.total,
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_err(e, "hipMemcpyAsync");
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+        plan->dev = dev_buf;
+        plan->waves = waves;
+        plan->ticket_base = 0;
+        plan->uploaded = true;
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+        if (!plan->uploaded) return set_err(SPTRSV_ERR_STATE, "plan not uploaded (or rewritten since)");
+        const int32_t n = plan->n;
+        if (n == 0) return SPTRSV_OK;
+        if (!b || !x) return set_err(SPTRSV_ERR_ARG, "null b or x");
+        const size_t nb = (size_t)n * sizeof(double);
+        if (overlaps(b, nb, x, nb)) return set_err(SPTRSV_ERR_ARG, "b and x overlap");
+        if (overlaps(x, nb, plan->dev, plan->layout.total) || overlaps(b, nb, plan->dev, plan->layout.total))
+            return set_err(SPTRSV_ERR_ARG, "b or x overlaps the plan buffer");
+        int waves = (int)std::min<int64_t>(plan->waves, ((plan->ntiles + 3) / 4) * 4);
+        if (waves < 4) waves = 4;
+        const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
+                                          plan->ntiles, waves, plan->ticket_base, plan->wait_limit, b, x,
+                                          stream);
+        if (e != 0) {
+            plan->uploaded = false;  // tile counter state unknown: force a fresh upload
+            return hip_err((hipError_t)e, "kernel launch");
+        }
+        plan->ticket_base += (unsigned long long)plan->ntiles + (unsigned long long)waves;
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_status) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan || !device_status) return set_err(SPTRSV_ERR_ARG, "null argument");
+        if (!plan->uploaded) return set_err(SPTRSV_ERR_STATE, "plan not uploaded");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+        unsigned char *ws = static_cast<unsigned char *>(plan->dev) + plan->layout.workspace;
+        unsigned int st = 0;
+        e = hipMemcpy(&st, ws + offsetof(sptrsv::Workspace, status), sizeof(st), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_err(e, "hipMemcpy");
+        const unsigned int zero = 0;
+        e = hipMemcpy(ws + offsetof(sptrsv::Workspace, status), &zero, sizeof(zero), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_err(e, "hipMemcpy");
+        *device_status = st ? SPTRSV_ERR_TIMEOUT : 0;
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks) {
+    if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+    plan->wait_limit = ticks;
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
+    if (!plan || !o) return set_err(SPTRSV_ERR_ARG, "null argument");
+    const sptrsv::Plan &p = *plan;
+    std::memset(o, 0, sizeof(*o));
+    o->n = p.n;
+    o->levels = p.nlev;
+    o->stages = p.nstages;
+    o->levels_rw = p.nlev_rw;
+    o->nnz = p.n ? p.rp[(size_t)p.n] : 0;
+    o->nnz_rw = p.lp_ptr.empty() ? 0 : p.lp_ptr.back();
+    o->nnz_m = p.m_ptr.empty() ? 0 : p.m_ptr.back();
+    o->flops = 2 * (o->nnz - p.n) + p.n;
+    o->flops_rw = 2 * (o->nnz_rw - p.n + o->nnz_m) + p.n;
+    o->bytes = 12 * o->nnz + 24 * (int64_t)p.n;
+    o->bytes_rw = 12 * (o->nnz_rw + o->nnz_m) + 24 * (int64_t)p.n;
+    o->device_bytes = (int64_t)p.layout.total;
+    o->tiles = p.ntiles;
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_plan_levels(sptrsv_plan plan, int32_t which, int32_t *level) {
+    if (!plan || (!level && plan->n > 0)) return set_err(SPTRSV_ERR_ARG, "null argument");
+    if (which != 0 && which != 1) return set_err(SPTRSV_ERR_ARG, "which must be 0 or 1");
+    const std::vector<int32_t> &v = which ? plan->level_rw : plan->level;
+    std::copy(v.begin(), v.end(), level);
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_plan_stages(sptrsv_plan plan, int32_t *stage_of_level, int64_t *delta_of_level) {
+    if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+    if (stage_of_level) std::copy(plan->stage_of_level.begin(), plan->stage_of_level.end(), stage_of_level);
+    if (delta_of_level) std::copy(plan->delta_of_level.begin(), plan->delta_of_level.end(), delta_of_level);
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_plan_schedule(sptrsv_plan plan, int32_t *level_ptr, int32_t *rows) {
+    if (!plan || !level_ptr || (!rows && plan->n > 0)) return set_err(SPTRSV_ERR_ARG, "null argument");
+    std::copy(plan->sched_ptr.begin(), plan->sched_ptr.end(), level_ptr);
+    std::copy(plan->sched_rows.begin(), plan->sched_rows.end(), rows);
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_col, double *lp_val,
+                                 int64_t *m_ptr, int32_t *m_col, double *m_val) {
+    if (!plan || !lp_ptr || !m_ptr) return set_err(SPTRSV_ERR_ARG, "null argument");
+    const sptrsv::Plan &p = *plan;
+    if ((!lp_col || !lp_val) && !p.lp_col.empty()) return set_err(SPTRSV_ERR_ARG, "null L' arrays");
+    if ((!m_col || !m_val) && !p.m_col.empty()) return set_err(SPTRSV_ERR_ARG, "null M arrays");
+    std::copy(p.lp_ptr.begin(), p.lp_ptr.end(), lp_ptr);
+    std::copy(p.lp_col.begin(), p.lp_col.end(), lp_col);
+    std::copy(p.lp_val.begin(), p.lp_val.end(), lp_val);
+    std::copy(p.m_ptr.begin(), p.m_ptr.end(), m_ptr);
+    std::copy(p.m_col.begin(), p.m_col.end(), m_col);
+    std::copy(p.m_val.begin(), p.m_val.end(), m_val);
+    return SPTRSV_OK;
+}
+
+void sptrsv_plan_destroy(sptrsv_plan plan) { delete plan; }
+
+const char *sptrsv_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// plan.hpp -- internal state of a plan and the host passes that build it.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sptrsv.h"
+
+namespace sptrsv {
+
+// Error carried out of the host passes; the C ABI turns it into a status
+// code and a thread-local message.
+struct Error {
+    sptrsv_status code;
+    std::string msg;
+};
+
+// Device image layout: byte offsets of each section inside the caller's
+// buffer.  Sections are 256-byte aligned.
+struct Layout {
+    size_t workspace = 0;  // Workspace block
+    size_t tiles = 0;      // int4[ntiles]  {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
+    size_t rows = 0;       // int32[n]      row id of each packed slot
+    size_t diag = 0;       // double[n]     diagonal of each packed slot
+    size_t tcol = 0;       // int32[64*nchunks] term column (>= 0 x-term, ~j b-term, INT32_MIN pad)
+    size_t tval = 0;       // double[64*nchunks] term coefficient (x-terms negated)
+    size_t total = 0;
+};
+
+// Per-solve bookkeeping shared by the kernels (lives at layout.workspace).
+struct Workspace {
+    unsigned long long ticket;  // monotone tile counter, never reset
+    unsigned int status;        // 0 ok, else SPTRSV_ERR_TIMEOUT
+    unsigned int pad0;
+    unsigned long long pad[6];
+};
+static_assert(sizeof(Workspace) == 64, "workspace block is one cache line");
+
+struct Plan {
+    // ---- analysed matrix (Sec. II / IV)
+    int32_t n = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> val;
+    std::vector<int32_t> level;  // level of each row of L
+    int32_t nlev = 0;
+    std::vector<int32_t> level_ptr, level_rows;
+
+    // ---- rewrite (Sec. III)
+    sptrsv_policy policy{};
+    std::vector<int32_t> stage_of_level;
+    std::vector<int64_t> delta_of_level;
+    int32_t nstages = 0;
+    std::vector<int64_t> lp_ptr, m_ptr;  // L' and M in CSR
+    std::vector<int32_t> lp_col, m_col;
+    std::vector<double> lp_val, m_val;
+    std::vector<int32_t> level_rw;  // levels of L'
+    int32_t nlev_rw = 0;
+    std::vector<int32_t> sched_ptr, sched_rows;
+
+    // ---- packed device image (host copy) and its layout
+    Layout layout;
+    std::vector<unsigned char> image;
+    int64_t ntiles = 0;
+    int64_t nchunks = 0;
+
+    // ---- device state
+    void *dev = nullptr;
+    bool uploaded = false;
+    unsigned long long ticket_base = 0;  // value of the tile counter at the next launch
+    int waves = 0;                       // waves launched per solve
+    uint64_t wait_limit = 200000000ull;  // 2 s at 100 MHz
+};
+
+// analyse.cpp
+void validate_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
+void analyse(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
+void level_sets(int32_t n, const int32_t *level, int32_t nlev, std::vector<int32_t> &ptr,
+                std::vector<int32_t> &rows);
+
+// rewrite.cpp
+void validate_policy(const sptrsv_policy &pol);
+void rewrite(Plan &p, const sptrsv_policy &pol);
+
+// pack.cpp
+void pack(Plan &p);
+
+}  // namespace sptrsv
+
+// solve.hip -- kernel launchers (return a hipError_t as int)
+extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay,
+                                   int32_t n, int64_t ntiles, int waves,
+                                   unsigned long long ticket_base, uint64_t wait_limit,
+                                   const double *b, double *x, void *stream);
+extern "C" int sptrsv_device_waves(int *waves);

@@ -1,0 +1,212 @@
+"""Host side of the C ABI (no GPU): the library loads and exports every
+declared entry point, rejects malformed input with the documented status,
+and its plans (levels, stages, rewritten structure and values, schedule)
+are bit-exact with the CPU oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_2103_11445_amd as m
+    m.load()
+    return m
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "sptrsv.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sptrsv_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(sp):
+    names = declared_functions()
+    assert "sptrsv_solve" in names and "sptrsv_analyse" in names and len(names) >= 15
+    lib = ctypes.CDLL(sp.library_path())
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _policy(kind, **kw):
+    return {"kind": kind, **kw}
+
+
+def compare_with_oracle(sp, s, pol):
+    kw = {k: v for k, v in pol.items() if k != "kind"}
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite(pol["kind"], **kw)
+    o = oracle.plan(s.row_ptr, s.col_idx, s.val, pol)
+    info = plan.info()
+    assert np.array_equal(plan.levels(0), o["level"])
+    assert info["levels"] == o["nlev"]
+    sol, dol = plan.stages()
+    assert np.array_equal(sol, o["stage_of_level"])
+    assert np.array_equal(dol, o["delta_of_level"])
+    assert info["stages"] == o["nstages"]
+    lp, m = plan.export()
+    for a, b in zip(lp, o["lp"]):
+        assert np.array_equal(a, b)
+    for a, b in zip(m, o["m"]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(plan.levels(1), o["level_rw"])
+    ptr, rows = plan.schedule()
+    assert np.array_equal(ptr, o["sched_ptr"]) and np.array_equal(rows, o["sched_rows"])
+    assert info["levels_rw"] == o["nlev_rw"]
+    assert info["nnz_rw"] == o["lp"][0][-1] and info["nnz_m"] == o["m"][0][-1]
+    assert info["flops"] == oracle.flops(s.row_ptr)
+    assert info["flops_rw"] == oracle.flops(o["lp"][0], o["m"][0])
+    assert info["bytes"] == 12 * s.nnz + 24 * s.n
+    assert info["bytes_rw"] == 12 * (info["nnz_rw"] + info["nnz_m"]) + 24 * s.n
+    return plan, o
+
+
+POLICIES = [
+    _policy("none"),
+    _policy("threshold"),
+    _policy("threshold", max_width=16, max_depth=64, max_fill=1.0),
+    _policy("threshold", max_width=10**9, max_depth=4, max_fill=10.0),
+    _policy("threshold", max_width=10**9, max_depth=10**9, max_fill=0.05, max_entries=40000),
+]
+
+
+@pytest.mark.parametrize("pol", POLICIES, ids=lambda p: str(p))
+@pytest.mark.parametrize("make", [
+    lambda: wl.stencil2d(100, seed=0),
+    lambda: wl.stencil3d(20, seed=1),
+    lambda: wl.banded(6000, 200, 8, 24, seed=2),
+    lambda: wl.powerlaw(50000, 1200, seed=3),
+    lambda: wl.random_lower(300, 0.05, seed=4),
+    lambda: wl.bidiagonal(500, seed=5),
+    lambda: wl.diagonal(77, seed=6),
+], ids=["2d", "3d", "banded", "powerlaw", "random", "chain", "diag"])
+def test_plan_bit_exact(sp, make, pol):
+    compare_with_oracle(sp, make(), pol)
+
+
+def test_explicit_masks_bit_exact(sp):
+    rng = np.random.default_rng(3)
+    s = wl.powerlaw(20000, 800, seed=9)
+    nlev = oracle.levels(s.row_ptr, s.col_idx)[1]
+    for t in range(5):
+        mask = (rng.random(nlev) < rng.uniform(0.2, 0.9)).astype(np.uint8)
+        compare_with_oracle(sp, s, {"kind": "explicit", "absorb": mask, "max_entries": 2**40})
+
+
+@pytest.mark.parametrize("name", ["stencil3d_128", "banded_1m", "powerlaw_4m"])
+def test_full_size_default_policy_bit_exact(sp, name):
+    """The large workload, at full size, under the default threshold rule."""
+    compare_with_oracle(sp, wl.config(name), _policy("threshold"))
+
+
+def test_rewrite_restarts_from_analysed_matrix(sp):
+    s = wl.powerlaw(30000, 900, seed=4)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    plan.rewrite("threshold", max_width=4, max_depth=16, max_fill=0.5)
+    first = plan.export()
+    plan.rewrite("threshold", max_width=10**9, max_depth=3, max_fill=9.0)
+    plan.rewrite("threshold", max_width=4, max_depth=16, max_fill=0.5)
+    again = plan.export()
+    for a, b in zip(first[0] + first[1], again[0] + again[1]):
+        assert np.array_equal(a, b)
+
+
+def test_empty_system(sp):
+    plan = sp.Plan(np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    i = plan.info()
+    assert i["n"] == 0 and i["levels"] == 0 and i["levels_rw"] == 0 and i["tiles"] == 0
+
+
+def test_policy_default(sp):
+    pol = sp.Policy()
+    sp.load().sptrsv_policy_default(ctypes.byref(pol))
+    assert (pol.kind, pol.max_width, pol.max_depth, pol.max_fill, pol.max_entries) == \
+        (1, 4, 64, 0.25, 2**31 - 1)
+
+
+# ------------------------------------------------------------- errors --
+
+def _analyse_status(sp, n, rp, ci, v):
+    lib = sp.load()
+    h = ctypes.c_void_p(123)
+    rp = None if rp is None else np.ascontiguousarray(rp, np.int32)
+    ci = None if ci is None else np.ascontiguousarray(ci, np.int32)
+    v = None if v is None else np.ascontiguousarray(v, np.float64)
+    p = lambda a: None if a is None else a.ctypes.data
+    st = lib.sptrsv_analyse(n, p(rp), p(ci), p(v), ctypes.byref(h))
+    if st == 0:
+        lib.sptrsv_plan_destroy(h)
+    else:
+        assert h.value is None  # *out = NULL on error
+        assert lib.sptrsv_last_error().decode() != ""
+    return sp.STATUS[st]
+
+
+def test_csr_errors(sp):
+    good_rp, good_ci, good_v = [0, 1, 3], [0, 0, 1], [2.0, -1.0, 3.0]
+    assert _analyse_status(sp, 2, good_rp, good_ci, good_v) == "OK"
+    cases = {
+        "ERR_ARG": [(-1, good_rp, good_ci, good_v), (2, None, good_ci, good_v),
+                    (2, good_rp, None, good_v), (2, good_rp, good_ci, None)],
+        "ERR_CSR": [(2, [1, 1, 3], good_ci, good_v),             # row_ptr[0] != 0
+                    (2, [0, 2, 1], [0, 0, 1], good_v),           # decreasing row_ptr
+                    (2, [0, 1, 3], [0, 5, 1], good_v),           # column out of range
+                    (2, [0, 1, 3], [0, -1, 1], good_v),          # negative column
+                    (3, [0, 1, 2, 5], [0, 1, 1, 0, 2], [1.0] * 5),  # unsorted
+                    (3, [0, 1, 2, 5], [0, 1, 0, 0, 2], [1.0] * 5),  # duplicate
+                    (2, [0, 2, 4], [0, 1, 0, 1], [1.0] * 4)],       # entry above diagonal
+        "ERR_DIAG": [(2, [0, 1, 2], [0, 0], [1.0, -1.0]),         # row 1 has no diagonal
+                     (2, [0, 1, 1], [0], [1.0]),                  # empty row
+                     (2, [0, 1, 3], [0, 0, 1], [2.0, -1.0, 0.0])],  # zero diagonal
+    }
+    for want, lst in cases.items():
+        for args in lst:
+            assert _analyse_status(sp, *args) == want, (want, args)
+    lib = sp.load()
+    assert sp.STATUS[lib.sptrsv_analyse(2, None, None, None, None)] == "ERR_ARG"
+
+
+def test_policy_errors(sp):
+    s = wl.stencil2d(5, seed=0)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    bad = [dict(kind="threshold", max_width=-1), dict(kind="threshold", max_depth=0),
+           dict(kind="threshold", max_fill=-0.5), dict(kind="threshold", max_fill=float("nan")),
+           dict(kind="threshold", max_entries=-1)]
+    for kw in bad:
+        kind = kw.pop("kind")
+        with pytest.raises(sp.SptrsvError) as e:
+            plan.rewrite(kind, **kw)
+        assert e.value.status == "ERR_ARG"
+    pol, _ = sp.make_policy("explicit")
+    pol.absorb_len = 3  # no mask pointer
+    assert sp.STATUS[sp.load().sptrsv_rewrite(plan._h, ctypes.byref(pol))] == "ERR_ARG"
+    pol.kind = 7
+    assert sp.STATUS[sp.load().sptrsv_rewrite(plan._h, ctypes.byref(pol))] == "ERR_ARG"
+    # a failed rewrite leaves a usable (plain) plan behind
+    info = plan.info()
+    assert info["levels_rw"] == info["levels"]
+
+
+def test_null_and_state_errors_without_gpu(sp):
+    lib = sp.load()
+    st = ctypes.c_int32()
+    for call in (lambda: lib.sptrsv_rewrite(None, None),
+                 lambda: lib.sptrsv_device_bytes(None, None),
+                 lambda: lib.sptrsv_plan_info(None, None),
+                 lambda: lib.sptrsv_solve(None, None, None, None),
+                 lambda: lib.sptrsv_check(None, None, ctypes.byref(st))):
+        assert sp.STATUS[call()] == "ERR_ARG"
+    s = wl.stencil2d(4, seed=0)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    assert sp.STATUS[lib.sptrsv_solve(plan._h, None, None, None)] == "ERR_STATE"
+    assert sp.STATUS[lib.sptrsv_check(plan._h, None, ctypes.byref(st))] == "ERR_STATE"
+    assert sp.STATUS[lib.sptrsv_upload(plan._h, None, 0, None)] == "ERR_ARG"
+    lib.sptrsv_plan_destroy(None)  # ignored

@@ -1,0 +1,145 @@
+"""GPU parity: the HIP solve (through the C ABI) against the CPU oracle, on
+the same seeded inputs, elementwise, max componentwise relative error
+<= 1e-10 against the FP64 serial substitution."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+from gate import TOL, errors
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_2103_11445_amd as m
+    m.load()
+    return m
+
+
+def relerr(x, ref):
+    """Floored componentwise relative error (see tests/gate.py)."""
+    return errors(x, ref)[1]
+
+
+def gpu_solve(torch, sp, s, kind="none", reps=1, **kw):
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite(kind, **kw).upload()
+    b = torch.from_numpy(np.ascontiguousarray(s.b)).cuda()
+    outs = []
+    for _ in range(reps):
+        x = torch.full_like(b, float("nan"))
+        plan.solve(b, x)
+        outs.append(x.cpu().numpy())
+    assert plan.check() == 0
+    return outs, plan
+
+
+POLICIES = [
+    ("none", {}),
+    ("threshold", {}),
+    ("threshold", {"max_width": 16, "max_depth": 64, "max_fill": 1.0}),
+    ("threshold", {"max_width": 10**9, "max_depth": 4, "max_fill": 10.0}),
+]
+
+
+@pytest.mark.parametrize("kind,kw", POLICIES)
+def test_stencil2d_small(torch, sp, kind, kw):
+    s = wl.stencil2d(100, seed=0)
+    ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
+    (x,), plan = gpu_solve(torch, sp, s, kind, **kw)
+    print(s.name, kind, kw, plan.info()["levels_rw"], relerr(x, ref), flush=True)
+    assert relerr(x, ref) <= TOL
+
+
+@pytest.mark.parametrize("make", [
+    lambda: wl.stencil3d(24, seed=11),
+    lambda: wl.banded(20011, 200, 8, 24, seed=12),
+    lambda: wl.powerlaw(100003, 1501, seed=13),
+    lambda: wl.random_lower(700, 0.6, seed=14),   # rows of hundreds of terms
+    lambda: wl.bidiagonal(4099, seed=15),          # one long chain
+    lambda: wl.diagonal(1000, seed=16),
+    lambda: wl.from_pairs(1, [], seed=17),
+    lambda: wl.from_pairs(65, [(64, j) for j in range(64)], seed=18),
+])
+@pytest.mark.parametrize("kind,kw", POLICIES)
+def test_families(torch, sp, make, kind, kw):
+    s = make()
+    ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
+    (x,), plan = gpu_solve(torch, sp, s, kind, **kw)
+    print(s.name, kind, kw, plan.info()["levels_rw"], relerr(x, ref), flush=True)
+    assert relerr(x, ref) <= TOL
+
+
+def test_rewritten_matches_oracle_rewritten_solve(torch, sp):
+    """The GPU solve of L' x = b + M b agrees with the oracle's serial solve of
+    the oracle's own rewritten system."""
+    s = wl.powerlaw(60000, 3000, seed=21)
+    pol = {"kind": "threshold", "max_width": 4, "max_depth": 64, "max_fill": 0.25}
+    o = oracle.plan(s.row_ptr, s.col_idx, s.val, pol)
+    ref = oracle.solve_rewritten(o["lp"], o["m"], s.b)
+    (x,), plan = gpu_solve(torch, sp, s, "threshold", max_width=4, max_depth=64, max_fill=0.25)
+    assert plan.info()["levels_rw"] == o["nlev_rw"]
+    assert relerr(x, ref) <= TOL
+
+
+def test_deterministic_and_no_sentinel(torch, sp):
+    """Each row's reduction order is fixed by the packing, so repeated solves
+    are bitwise identical; no output keeps the not-ready pattern."""
+    s = wl.powerlaw(50000, 2000, seed=22)
+    outs, _ = gpu_solve(torch, sp, s, "threshold", reps=20)
+    for o in outs[1:]:
+        assert np.array_equal(o.view(np.int64), outs[0].view(np.int64))
+    assert np.all(np.isfinite(outs[0]))
+
+
+def test_empty_system(torch, sp):
+    s = wl.from_pairs(0, [], seed=0)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    plan.upload()
+    b = torch.zeros(0, dtype=torch.float64, device="cuda")
+    x = plan.solve(b)
+    assert x.numel() == 0
+
+
+def test_wait_limit_reports_timeout_and_recovers(torch, sp):
+    """A wait limit of 0 ticks makes every wait that is not satisfied on its
+    first poll give up: the kernel still drains, the status word reports a
+    timeout, and the next solve with a normal limit is correct."""
+    s = wl.bidiagonal(2000, seed=23)
+    ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).upload()
+    b = torch.from_numpy(s.b).cuda()
+    plan.set_wait_limit(0)
+    plan.solve(b)
+    assert plan.check() == 8  # SPTRSV_ERR_TIMEOUT
+    plan.set_wait_limit(200_000_000)
+    x = plan.solve(b)
+    assert plan.check() == 0
+    assert relerr(x.cpu().numpy(), ref) <= TOL
+
+
+def test_solve_state_errors(torch, sp):
+    s = wl.stencil2d(10, seed=1)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    b = torch.from_numpy(s.b).cuda()
+    with pytest.raises(sp.SptrsvError) as e:
+        plan.solve(b)
+    assert e.value.status == "ERR_STATE"
+    plan.upload()
+    with pytest.raises(sp.SptrsvError) as e:
+        plan.solve(b, b)
+    assert e.value.status == "ERR_ARG"
+    plan.rewrite("threshold")
+    with pytest.raises(sp.SptrsvError) as e:
+        plan.solve(b)
+    assert e.value.status == "ERR_STATE"
