@@ -129,9 +129,9 @@ sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void 
 
 /* Solves L x = b (device arrays of n doubles, b != x, neither overlapping
  * the plan buffer) with the uploaded schedule: enqueues one fill of x and one
- * solve kernel on stream and returns without waiting.  Every row waits only
- * for the rows it still depends on (per-row readiness, in level order), so
- * the level structure bounds the critical path.  Numerical problems are not
+ * cooperative solve kernel on stream and returns without waiting.  Every
+ * row waits only for the rows it still depends on (per-row readiness, in
+ * level order), so the level structure bounds the critical path.  Numerical problems are not
  * reported (zero diagonals were rejected by analyse); a dependency wait
  * that exceeds the wait limit is reported by sptrsv_check.  Errors: ARG,
  * STATE (not uploaded or stale), HIP. */
@@ -141,6 +141,12 @@ sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *s
  * *device_status = 0 if every solve since the last check completed normally,
  * else SPTRSV_ERR_TIMEOUT.  Errors: ARG, STATE, HIP. */
 sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_status);
+
+/* Launch shape of the solve: waves (one per workgroup, all co-resident) per
+ * compute unit, capped by what the device can keep resident; 0 (the
+ * default) picks 1..8 from the plan's tiles per level.  Takes effect at the
+ * next solve.  Errors: ARG (negative). */
+sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu);
 
 /* Upper bound, in ticks of the 100 MHz GPU real-time clock, on a single
  * dependency wait (default 200,000,000 = 2 s).  A wait that reaches it

@@ -79,6 +79,7 @@ def load():
         "sptrsv_solve": (S, [P, P, P, P]),
         "sptrsv_check": (S, [P, P, P]),
         "sptrsv_set_wait_limit": (S, [P, U64]),
+        "sptrsv_set_launch": (S, [P, I32]),
         "sptrsv_plan_info": (S, [P, P]),
         "sptrsv_plan_levels": (S, [P, I32, P]),
         "sptrsv_plan_stages": (S, [P, P, P]),
@@ -180,6 +181,10 @@ class Plan:
              np.empty(i["nnz_m"], np.float64))
         _check(load().sptrsv_plan_export(self._h, *(_ptr(a) for a in lp), *(_ptr(a) for a in m)))
         return lp, m
+
+    def set_launch(self, waves_per_cu: int = 0):
+        _check(load().sptrsv_set_launch(self._h, int(waves_per_cu)))
+        return self
 
     def set_wait_limit(self, ticks: int):
         _check(load().sptrsv_set_wait_limit(self._h, int(ticks)))

@@ -41,6 +41,23 @@ sptrsv_status hip_err(hipError_t e, const char *what) {
     return set_err(SPTRSV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Waves of the cooperative solve grid.  Unless set by sptrsv_set_launch, the
+// count follows the work per level: about two waves per CU for every CU's
+// worth of tiles in an average level (1 to 8 per CU), because waves that
+// run far ahead of the frontier only poll.
+int launch_waves(const sptrsv::Plan &p) {
+    int wpc = p.waves_per_cu;
+    if (wpc <= 0) {
+        const double per_level = p.nlev_rw > 0 ? (double)p.ntiles / p.nlev_rw : 0.0;
+        const double want = 2.0 * per_level / std::max(1, p.cus);
+        wpc = 1;
+        while (wpc < 8 && wpc * 2 <= want) wpc *= 2;
+    }
+    wpc = std::min(wpc, p.max_waves_per_cu);
+    const int64_t w = std::min<int64_t>((int64_t)p.cus * wpc, p.ntiles);
+    return (int)std::max<int64_t>(1, w);
+}
+
 bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
     const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
     return pa < pb + bn && pb < pa + an;
@@ -113,8 +130,9 @@ sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void 
             return set_err(SPTRSV_ERR_ARG, "device buffer smaller than sptrsv_device_bytes");
         if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0)
             return set_err(SPTRSV_ERR_ARG, "device buffer not 256-byte aligned");
-        int waves = 0;
-        if (int e = sptrsv_device_waves(&waves)) return hip_err((hipError_t)e, "device query");
+        int cus = 0, maxw = 0;
+        if (int e = sptrsv_device_limits(&cus, &maxw)) return hip_err((hipError_t)e, "device query");
+        if (cus <= 0 || maxw <= 0) return set_err(SPTRSV_ERR_HIP, "solve kernel cannot be resident");
         hipStream_t s = static_cast<hipStream_t>(stream);
         hipError_t e = hipMemcpyAsync(dev_buf, plan->image.data(), plan->layout.total,
                                       hipMemcpyHostToDevice, s);
@@ -122,8 +140,8 @@ sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void 
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_err(e, "hipStreamSynchronize");
         plan->dev = dev_buf;
-        plan->waves = waves;
-        plan->ticket_base = 0;
+        plan->cus = cus;
+        plan->max_waves_per_cu = maxw;
         plan->uploaded = true;
         return SPTRSV_OK;
     });
@@ -140,16 +158,10 @@ sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *s
         if (overlaps(b, nb, x, nb)) return set_err(SPTRSV_ERR_ARG, "b and x overlap");
         if (overlaps(x, nb, plan->dev, plan->layout.total) || overlaps(b, nb, plan->dev, plan->layout.total))
             return set_err(SPTRSV_ERR_ARG, "b or x overlaps the plan buffer");
-        int waves = (int)std::min<int64_t>(plan->waves, ((plan->ntiles + 3) / 4) * 4);
-        if (waves < 4) waves = 4;
+        const int waves = launch_waves(*plan);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
-                                          plan->ntiles, waves, plan->ticket_base, plan->wait_limit, b, x,
-                                          stream);
-        if (e != 0) {
-            plan->uploaded = false;  // tile counter state unknown: force a fresh upload
-            return hip_err((hipError_t)e, "kernel launch");
-        }
-        plan->ticket_base += (unsigned long long)plan->ntiles + (unsigned long long)waves;
+                                          plan->ntiles, waves, plan->wait_limit, b, x, stream);
+        if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
 }
@@ -171,6 +183,13 @@ sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_statu
         *device_status = st ? SPTRSV_ERR_TIMEOUT : 0;
         return SPTRSV_OK;
     });
+}
+
+sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu) {
+    if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+    if (waves_per_cu < 0) return set_err(SPTRSV_ERR_ARG, "waves_per_cu < 0");
+    plan->waves_per_cu = waves_per_cu;
+    return SPTRSV_OK;
 }
 
 sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks) {

@@ -31,10 +31,9 @@ struct Layout {
 
 // Per-solve bookkeeping shared by the kernels (lives at layout.workspace).
 struct Workspace {
-    unsigned long long ticket;  // monotone tile counter, never reset
-    unsigned int status;        // 0 ok, else SPTRSV_ERR_TIMEOUT
+    unsigned int status;  // 0 ok, else SPTRSV_ERR_TIMEOUT; cleared by sptrsv_check
     unsigned int pad0;
-    unsigned long long pad[6];
+    unsigned long long pad[7];
 };
 static_assert(sizeof(Workspace) == 64, "workspace block is one cache line");
 
@@ -68,8 +67,9 @@ struct Plan {
     // ---- device state
     void *dev = nullptr;
     bool uploaded = false;
-    unsigned long long ticket_base = 0;  // value of the tile counter at the next launch
-    int waves = 0;                       // waves launched per solve
+    int cus = 0;                         // compute units of the device uploaded to
+    int max_waves_per_cu = 0;            // co-resident solve workgroups per CU
+    int waves_per_cu = 0;                // requested; 0 = chosen from the plan's shape
     uint64_t wait_limit = 200000000ull;  // 2 s at 100 MHz
 };
 
@@ -90,7 +90,6 @@ void pack(Plan &p);
 
 // solve.hip -- kernel launchers (return a hipError_t as int)
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay,
-                                   int32_t n, int64_t ntiles, int waves,
-                                   unsigned long long ticket_base, uint64_t wait_limit,
+                                   int32_t n, int64_t ntiles, int waves, uint64_t wait_limit,
                                    const double *b, double *x, void *stream);
-extern "C" int sptrsv_device_waves(int *waves);
+extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu);
