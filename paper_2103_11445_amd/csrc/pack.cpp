@@ -1,16 +1,26 @@
 // pack.cpp -- device image of a plan: the executed schedule (level sets of
-// L'), cut into 64-lane work tiles, and the rows' terms in a sliced,
-// lane-interleaved layout so that every chunk of a tile is one coalesced
-// 64-lane load.
+// L') as a list of work items in level order.
 //
-// Within a level, rows are binned by term count (b-terms + x-terms): a row
-// of `len` terms gets g lanes, the smallest power of two with
+// Wide items.  Within a level, rows are binned by term count (b-terms +
+// x-terms): a row of `len` terms gets g lanes, the smallest power of two with
 // len <= kTermsPerLane * g (capped at 64).  A tile holds 64/g rows of one bin
 // of one level; its terms occupy `nchunks` chunks of 64 slots, the t-th term
 // of the tile's r-th row at chunk t / g, lane r * g + t % g.  Each row lists
 // its b-terms (column ~j, coefficient M_ij) before its x-terms (column k,
-// coefficient -L'_ik); unused slots hold INT32_MIN.  Tiles are ordered by
-// level, so a tile only depends on tiles before it.
+// coefficient -L'_ik); unused slots hold INT32_MIN.
+//
+// Segments.  A level is narrow when its rows fit in at most kNarrowTiles
+// tiles of kSegChunks chunks (g = 64 / rows-per-tile, as many lanes per row
+// as the tile allows).  A run of at least kMinSegLevels narrow levels is a
+// segment, executed by one wave from first tile to last: dependencies on
+// rows of the same segment produced at most kRing rows earlier are read
+// from the wave's LDS ring (column n + ring index) instead of global memory.
+// Segment tiles are stored with a fixed stride, lane-major (each lane's
+// kSegChunks columns, then its coefficients, contiguous; one row id / meta
+// pair and one diagonal per lane) so the wave prefetches a tile with a few
+// wide loads, several tiles ahead, without reading a descriptor first.
+//
+// Items are ordered by level, so an item only depends on items before it.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -32,23 +42,86 @@ int bin_of(int64_t len) {
     while (lg < kBins - 1 && len > (int64_t)kTermsPerLane << lg) ++lg;
     return lg;
 }
+
+// log2 of the lanes per row of a segment tile whose longest row has
+// `maxlen` terms (kSegChunks chunks), or -1 if no width fits.
+int seg_lanes_log2(int64_t maxlen) {
+    for (int lg = 0; lg <= 6; ++lg)
+        if (maxlen <= (int64_t)kSegChunks << lg) return lg;
+    return -1;
+}
 }  // namespace
 
 void pack(Plan &p) {
     const int32_t n = p.n;
+    if ((int64_t)n + kRing > INT32_MAX)
+        throw Error{SPTRSV_ERR_OVERFLOW, "n too large for the device encoding"};
     std::vector<int64_t> len((size_t)n);
     for (int32_t i = 0; i < n; ++i)
         len[(size_t)i] = (p.lp_ptr[(size_t)i + 1] - p.lp_ptr[(size_t)i] - 1) +
                          (p.m_ptr[(size_t)i + 1] - p.m_ptr[(size_t)i]);
 
-    // ---- order rows inside each level by bin, and cut tiles
+    // ---- classify levels: narrow levels and their segment tile shape
+    const int32_t L = p.nlev_rw;
+    std::vector<int8_t> seg_lg((size_t)L, -1);  // lanes-per-row log2 if narrow
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t b0 = p.sched_ptr[(size_t)l], b1 = p.sched_ptr[(size_t)l + 1];
+        int64_t mx = 0;
+        for (int32_t q = b0; q < b1; ++q) mx = std::max(mx, len[(size_t)p.sched_rows[(size_t)q]]);
+        const int lg = seg_lanes_log2(mx);
+        if (lg < 0) continue;
+        const int32_t per = 64 >> lg;
+        if ((b1 - b0 + per - 1) / per <= kNarrowTiles) seg_lg[(size_t)l] = (int8_t)lg;
+    }
+    std::vector<char> in_seg((size_t)L, 0);
+    for (int32_t l = 0; l < L;) {
+        int32_t e = l;
+        while (e < L && seg_lg[(size_t)e] >= 0) ++e;
+        if (e - l >= kMinSegLevels)
+            for (int32_t q = l; q < e; ++q) in_seg[(size_t)q] = 1;
+        l = std::max(e, l + 1);
+    }
+
+    // ---- order rows and cut items
     std::vector<int32_t> slot_row((size_t)n);
     struct Tile { int64_t chunk_off; int32_t row_off, nch, nrows, lg; };
+    struct SegTile { int32_t row_off, nrows, lg; };
+    struct Item { int kind; int64_t a, b; };  // wide: a = wide tile; seg: a = first seg tile, b = count
     std::vector<Tile> tiles;
+    std::vector<SegTile> stiles;
+    std::vector<Item> items;
+    std::vector<int32_t> seg_of_slot((size_t)n, -1);   // segment id of each slot
+    std::vector<int32_t> seg_tile_first;                // first slot of each segment tile
     int64_t nchunks = 0;
-    int32_t slot = 0;
-    for (int32_t l = 0; l < p.nlev_rw; ++l) {
+    int32_t slot = 0, nseg = 0;
+    for (int32_t l = 0; l < L; ++l) {
         const int32_t b0 = p.sched_ptr[(size_t)l], b1 = p.sched_ptr[(size_t)l + 1];
+        if (in_seg[(size_t)l]) {
+            if (l == 0 || !in_seg[(size_t)l - 1]) {
+                items.push_back({1, (int64_t)stiles.size(), 0});
+                ++nseg;
+            }
+            const int lg = seg_lg[(size_t)l];
+            const int32_t per = 64 >> lg;
+            for (int32_t q = b0; q < b1; ++q) {
+                slot_row[(size_t)(slot + q - b0)] = p.sched_rows[(size_t)q];
+                seg_of_slot[(size_t)(slot + q - b0)] = nseg - 1;
+            }
+            for (int32_t s = slot; s < slot + (b1 - b0); s += per) {
+                stiles.push_back({s, std::min(per, slot + (b1 - b0) - s), lg});
+                items.back().b += 1;
+            }
+            slot += b1 - b0;
+            if (l + 1 == L || !in_seg[(size_t)l + 1]) {
+                // pad the segment to a whole number of pipeline steps with
+                // empty tiles (no rows, no terms)
+                while (items.back().b % kSegDepth) {
+                    stiles.push_back({slot, 0, 0});
+                    items.back().b += 1;
+                }
+            }
+            continue;
+        }
         int32_t cnt[kBins] = {0};
         for (int32_t q = b0; q < b1; ++q) ++cnt[bin_of(len[(size_t)p.sched_rows[(size_t)q]])];
         int32_t start[kBins];
@@ -70,67 +143,140 @@ void pack(Plan &p) {
                 int64_t mx = 0;
                 for (int32_t r = 0; r < nr; ++r) mx = std::max(mx, len[(size_t)slot_row[(size_t)(s + r)]]);
                 const int64_t nch = (mx + (1 << g) - 1) >> g;
+                items.push_back({0, (int64_t)tiles.size(), 0});
                 tiles.push_back({nchunks, s, (int32_t)nch, nr, g});
                 nchunks += nch;
             }
         }
         slot = acc;
     }
-    if (nchunks > INT32_MAX || (int64_t)tiles.size() > INT32_MAX)
+    if (nchunks > INT32_MAX || (int64_t)items.size() > INT32_MAX || (int64_t)stiles.size() * 64 > INT32_MAX)
         throw Error{SPTRSV_ERR_OVERFLOW, "device image needs more than INT32_MAX chunks"};
+    std::vector<int32_t> slot_of_row((size_t)n);
+    for (int32_t s = 0; s < n; ++s) slot_of_row[(size_t)slot_row[(size_t)s]] = s;
+    // first slot of every segment (for ring positions)
+    std::vector<int32_t> seg_first((size_t)nseg, 0);
+    {
+        int32_t sid = -1;
+        for (const Item &it : items)
+            if (it.kind == 1) seg_first[(size_t)++sid] = stiles[(size_t)it.a].row_off;
+    }
 
     // ---- layout
-    Layout &L = p.layout;
+    const int64_t nst = (int64_t)stiles.size();
+    Layout &Ly = p.layout;
     size_t off = 0;
-    L.workspace = off;
+    Ly.workspace = off;
     off = align256(off + sizeof(Workspace));
-    L.tiles = off;
-    off = align256(off + tiles.size() * 16);
-    L.rows = off;
+    Ly.tiles = off;
+    off = align256(off + items.size() * 16);
+    Ly.rows = off;
     off = align256(off + (size_t)n * 4);
-    L.diag = off;
+    Ly.diag = off;
     off = align256(off + (size_t)n * 8);
-    L.tcol = off;
+    Ly.tcol = off;
     off = align256(off + (size_t)nchunks * 64 * 4);
-    L.tval = off;
+    Ly.tval = off;
     off = align256(off + (size_t)nchunks * 64 * 8);
-    L.total = off;
+    Ly.scol = off;
+    off = align256(off + (size_t)nst * kSegChunks * 64 * 4);
+    Ly.sval = off;
+    off = align256(off + (size_t)nst * kSegChunks * 64 * 8);
+    Ly.srow = off;
+    off = align256(off + (size_t)nst * 64 * 8);
+    Ly.sdiag = off;
+    off = align256(off + (size_t)nst * 64 * 8);
+    Ly.total = off;
 
-    p.image.assign(L.total, 0);
+    p.image.assign(Ly.total, 0);
     unsigned char *img = p.image.data();
-    int32_t *trow = reinterpret_cast<int32_t *>(img + L.rows);
-    double *tdiag = reinterpret_cast<double *>(img + L.diag);
-    int32_t *tcol = reinterpret_cast<int32_t *>(img + L.tcol);
-    double *tval = reinterpret_cast<double *>(img + L.tval);
-    int32_t *tdesc = reinterpret_cast<int32_t *>(img + L.tiles);
+    int32_t *trow = reinterpret_cast<int32_t *>(img + Ly.rows);
+    double *tdiag = reinterpret_cast<double *>(img + Ly.diag);
+    int32_t *tcol = reinterpret_cast<int32_t *>(img + Ly.tcol);
+    double *tval = reinterpret_cast<double *>(img + Ly.tval);
+    int32_t *desc = reinterpret_cast<int32_t *>(img + Ly.tiles);
+    int32_t *scol = reinterpret_cast<int32_t *>(img + Ly.scol);
+    double *sval = reinterpret_cast<double *>(img + Ly.sval);
+    int32_t *srow = reinterpret_cast<int32_t *>(img + Ly.srow);  // {row, meta} per lane
+    double *sdiag = reinterpret_cast<double *>(img + Ly.sdiag);
     std::fill(tcol, tcol + nchunks * 64, kPad);
-    for (size_t t = 0; t < tiles.size(); ++t) {
-        const Tile &T = tiles[t];
-        tdesc[4 * t + 0] = (int32_t)T.chunk_off;
-        tdesc[4 * t + 1] = T.row_off;
-        tdesc[4 * t + 2] = T.nch;
-        tdesc[4 * t + 3] = (T.nrows << 8) | T.lg;
+    std::fill(scol, scol + nst * kSegChunks * 64, kPad);
+    for (int64_t q = 0; q < nst * 64; ++q) srow[2 * q] = -1;
+    for (int32_t s = 0; s < n; ++s) {
+        const int32_t i = slot_row[(size_t)s];
+        trow[s] = i;
+        tdiag[s] = p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1];
+    }
+
+    // terms of row i for a tile with 2^lg lanes per row, written through put(col, val)
+    auto row_terms = [&](int32_t i, int32_t seg, int32_t first_slot_of_tile, auto &&put) {
+        for (int64_t q = p.m_ptr[(size_t)i]; q < p.m_ptr[(size_t)i + 1]; ++q)
+            put(~p.m_col[(size_t)q], p.m_val[(size_t)q]);
+        for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q) {
+            const int32_t k = p.lp_col[(size_t)q];
+            int32_t col = k;
+            if (seg >= 0) {
+                const int32_t sk = slot_of_row[(size_t)k];
+                if (seg_of_slot[(size_t)sk] == seg && first_slot_of_tile - sk <= kRing)
+                    col = n + ((sk - seg_first[(size_t)seg]) & (kRing - 1));
+            }
+            put(col, -p.lp_val[(size_t)q]);
+        }
+    };
+
+    int32_t sid = -1;
+    for (size_t it = 0; it < items.size(); ++it) {
+        const Item &I = items[it];
+        if (I.kind == 1) {
+            ++sid;
+            desc[4 * it + 0] = (int32_t)I.a;
+            desc[4 * it + 1] = (int32_t)I.b;
+            desc[4 * it + 2] = 0;
+            desc[4 * it + 3] = (int32_t)0x80000000u;
+            for (int64_t st = I.a; st < I.a + I.b; ++st) {
+                const SegTile &T = stiles[(size_t)st];
+                const int32_t g = 1 << T.lg;
+                for (int32_t lane = 0; lane < 64; ++lane) srow[2 * (st * 64 + lane) + 1] = T.lg;
+                for (int32_t r = 0; r < T.nrows; ++r) {
+                    const int32_t s = T.row_off + r;
+                    const int32_t i = slot_row[(size_t)s];
+                    const int64_t lead = st * 64 + r * g;
+                    srow[2 * lead] = i;
+                    srow[2 * lead + 1] = T.lg | (((s - seg_first[(size_t)sid]) & (kRing - 1)) << 8);
+                    sdiag[lead] = tdiag[s];
+                    int64_t t_ = 0;
+                    row_terms(i, sid, T.row_off, [&](int32_t col, double v) {
+                        const int64_t ln = st * 64 + r * g + (t_ & (g - 1));
+                        const int64_t idx = ln * kSegChunks + (t_ >> T.lg);
+                        scol[idx] = col;
+                        sval[idx] = v;
+                        ++t_;
+                    });
+                }
+            }
+            continue;
+        }
+        const Tile &T = tiles[(size_t)I.a];
+        desc[4 * it + 0] = (int32_t)T.chunk_off;
+        desc[4 * it + 1] = T.row_off;
+        desc[4 * it + 2] = T.nch;
+        desc[4 * it + 3] = (T.nrows << 8) | T.lg;
         const int32_t g = 1 << T.lg;
         for (int32_t r = 0; r < T.nrows; ++r) {
-            const int32_t s = T.row_off + r;
-            const int32_t i = slot_row[(size_t)s];
-            trow[s] = i;
-            tdiag[s] = p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1];
+            const int32_t i = slot_row[(size_t)(T.row_off + r)];
             int64_t t_ = 0;
-            auto put = [&](int32_t col, double v) {
+            row_terms(i, -1, 0, [&](int32_t col, double v) {
                 const int64_t idx = (T.chunk_off + (t_ >> T.lg)) * 64 + r * g + (t_ & (g - 1));
                 tcol[idx] = col;
                 tval[idx] = v;
                 ++t_;
-            };
-            for (int64_t q = p.m_ptr[(size_t)i]; q < p.m_ptr[(size_t)i + 1]; ++q)
-                put(~p.m_col[(size_t)q], p.m_val[(size_t)q]);
-            for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q)
-                put(p.lp_col[(size_t)q], -p.lp_val[(size_t)q]);
+            });
         }
     }
-    p.ntiles = (int64_t)tiles.size();
+    p.ntiles = (int64_t)items.size();
     p.nchunks = nchunks;
+    p.nseg = nseg;
+    p.nseg_tiles = nst;
     p.uploaded = false;
 }
 

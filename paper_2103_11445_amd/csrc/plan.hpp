@@ -17,15 +17,28 @@ struct Error {
     std::string msg;
 };
 
+// Shape constants of the device image shared by the packer and the kernels.
+constexpr int kSegChunks = 4;     // chunks per segment tile
+constexpr int kRing = 2048;       // x values a segment wave keeps in LDS (power of two)
+constexpr int kNarrowTiles = 2;   // a level of at most this many segment tiles is narrow
+constexpr int kMinSegLevels = 16; // shortest run of narrow levels executed as a segment
+constexpr int kSegDepth = 4;      // segment software-pipeline depth; segments hold a multiple of it
+
 // Device image layout: byte offsets of each section inside the caller's
 // buffer.  Sections are 256-byte aligned.
 struct Layout {
     size_t workspace = 0;  // Workspace block
-    size_t tiles = 0;      // int4[ntiles]  {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
+    size_t tiles = 0;      // int4[nitems]: wide tile {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
+                           //   or segment {first segment tile, count, 0, 1<<31}
     size_t rows = 0;       // int32[n]      row id of each packed slot
     size_t diag = 0;       // double[n]     diagonal of each packed slot
-    size_t tcol = 0;       // int32[64*nchunks] term column (>= 0 x-term, ~j b-term, INT32_MIN pad)
+    size_t tcol = 0;       // int32[64*nchunks] term column (0..n-1 x-term, ~j b-term, INT32_MIN pad)
     size_t tval = 0;       // double[64*nchunks] term coefficient (x-terms negated)
+    size_t scol = 0;       // int32[nseg_tiles][64][kSegChunks] as tcol, plus n + ring index for LDS x-terms
+    size_t sval = 0;       // double[nseg_tiles][64][kSegChunks]
+    size_t srow = 0;       // int32[nseg_tiles][64][2]: row finished by the lane (-1 if none),
+                           //   log2 lanes per row | ring index << 8
+    size_t sdiag = 0;      // double[nseg_tiles][64] its diagonal
     size_t total = 0;
 };
 
@@ -61,8 +74,10 @@ struct Plan {
     // ---- packed device image (host copy) and its layout
     Layout layout;
     std::vector<unsigned char> image;
-    int64_t ntiles = 0;
+    int64_t ntiles = 0;      // work items (wide tiles and segments)
     int64_t nchunks = 0;
+    int32_t nseg = 0;        // segments
+    int64_t nseg_tiles = 0;  // tiles inside segments
 
     // ---- device state
     void *dev = nullptr;
@@ -90,6 +105,6 @@ void pack(Plan &p);
 
 // solve.hip -- kernel launchers (return a hipError_t as int)
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay,
-                                   int32_t n, int64_t ntiles, int waves, uint64_t wait_limit,
+                                   int32_t n, int64_t nitems, int waves, uint64_t wait_limit,
                                    const double *b, double *x, void *stream);
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu);

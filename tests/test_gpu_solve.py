@@ -112,10 +112,11 @@ def test_empty_system(torch, sp):
 
 
 def test_wait_limit_reports_timeout_and_recovers(torch, sp):
-    """A wait limit of 0 ticks makes every wait that is not satisfied on its
-    first poll give up: the kernel still drains, the status word reports a
-    timeout, and the next solve with a normal limit is correct."""
-    s = wl.bidiagonal(2000, seed=23)
+    """A wait limit of 0 ticks makes every cross-wave wait that is not
+    satisfied on its first poll give up: the kernel still drains, the status
+    word reports a timeout, and the next solve with a normal limit is
+    correct.  (Wide levels, so that rows wait on other waves.)"""
+    s = wl.stencil3d(24, seed=23)
     ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
     plan = sp.Plan(s.row_ptr, s.col_idx, s.val).upload()
     b = torch.from_numpy(s.b).cuda()
