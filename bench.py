@@ -5,14 +5,19 @@ MI355X.
 One step = one solve of each of the three large synthetic systems (3D 7-point
 stencil on 128^3, random banded n=1e6 / bandwidth 200, power-law n=4e6 with a
 20k-row serial tail), FP64, one right-hand side each, with every input
-already resident in HBM.  The rewrite (host analysis) happens before the
-timed region, once per matrix, as a factorisation would.  Reported:
+already resident in HBM.  Analysis and rewriting are host passes done once
+per matrix before the timed region (as a factorisation would be); their time
+is reported per matrix.
 
-  value        solves/s over the timed steps (3 solves per step)
-  roofline     algorithmic bytes of the rewritten solves / their measured
-               time, against 8 TB/s HBM
-  plain        the same kernel on the plain level-set schedule (no rewrite)
-  cpu_baseline the serial FP64 CPU oracle on the host, on a bounded sample
+Legs, in order:
+  cpu_baseline  the serial FP64 CPU oracle on the host, on a bounded sample;
+                its solutions are also the references of the parity check
+  tune          per matrix, the rewrite policy with the fastest measured
+                solve among a few candidates of the threshold rule
+                (--no-tune uses the table TUNED)
+  timed         --steps steps after --warmup, timed with HIP events on the
+                stream the kernels run on
+  plain         the same kernel on the plain level-set schedule
 """
 from __future__ import annotations
 
@@ -30,16 +35,25 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 from gate import TOL, errors  # noqa: E402  (floored componentwise error, see tests/gate.py)
 
 HBM_PEAK_GBS = 8000.0
-
-# Rewrite policy per workload (threshold rule of the paper's thin-level
-# rewriting with GPU-sized parameters; see the design doc for how they were chosen).
-POLICIES = {
-    "stencil3d_128": {"kind": "threshold", "max_width": 4, "max_depth": 64, "max_fill": 0.25},
-    "banded_1m": {"kind": "threshold", "max_width": 4, "max_depth": 64, "max_fill": 0.25},
-    "powerlaw_4m": {"kind": "threshold", "max_width": 4, "max_depth": 64, "max_fill": 0.25},
-}
 LARGE = ["stencil3d_128", "banded_1m", "powerlaw_4m"]
 SMALL = ["stencil2d_100"]
+INF = 10**9
+
+# Candidate policies of the threshold rule.  "paper" is the thin-level rule
+# with its default parameters; "depthD" absorbs every level into stages of D
+# levels (every level is thin for a GPU that runs thousands of rows at once),
+# with at most 12 x nnz(L) added entries.
+CANDIDATES = {
+    "plain": ("none", {}),
+    "paper": ("threshold", {"max_width": 4, "max_depth": 64, "max_fill": 0.25}),
+    "depth2": ("threshold", {"max_width": INF, "max_depth": 2, "max_fill": 12.0}),
+    "depth4": ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 12.0}),
+    "depth8": ("threshold", {"max_width": INF, "max_depth": 8, "max_fill": 12.0}),
+    "depth16": ("threshold", {"max_width": INF, "max_depth": 16, "max_fill": 12.0}),
+}
+# Result of the tuning leg on MI355X (used by --no-tune, e.g. under a profiler).
+TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth16", "powerlaw_4m": "paper",
+         "stencil2d_100": "paper"}
 
 
 def log(*a):
@@ -50,19 +64,31 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["large", "small"], default="large")
-    ap.add_argument("--plain-steps", type=int, default=None)
+    ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU leg (and the parity check)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the solve is not sharded across GPUs "
-              "(see DESIGN.md, 'How it would shard'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the solve is not sharded across GPUs (DESIGN.md, "
+              "'How it would shard'); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 5}), flush=True)
+        return
 
     import paper_2103_11445_amd as sp
     import workloads
@@ -70,43 +96,98 @@ def main():
     sp.load()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
     names = LARGE if args.workload == "large" else SMALL
 
-    systems, plans, plain, bs, xs, host = {}, {}, {}, {}, {}, {}
+    systems, host = {}, {}
     for name in names:
         t0 = time.perf_counter()
-        s = workloads.config(name)
-        t1 = time.perf_counter()
-        pol = dict(POLICIES.get(name, {"kind": "threshold"}))
-        kind = pol.pop("kind")
+        systems[name] = workloads.config(name)
+        host[name] = {"generate_s": time.perf_counter() - t0}
+        log(f"[setup] {name}: n={systems[name].n} nnz={systems[name].nnz}")
+
+    # ---- CPU leg: the oracle, timed on the host; its x are the references
+    refs, cpu = {}, None
+    if not args.no_cpu:
+        import oracle
+        t_total, count = 0.0, 0
+        t0 = time.perf_counter()
+        while True:
+            for n in names:
+                s = systems[n]
+                refs[n] = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
+                count += 1
+            t_total = time.perf_counter() - t0
+            if t_total >= args.cpu_seconds:
+                break
+        cpu = {"value": count / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"serial FP64 forward substitution (the oracle) over the same "
+                         f"{len(names)} systems, cycled {count // len(names)} times in {t_total:.1f} s "
+                         f"on one host core"}
+        log(f"[cpu] {cpu}")
+
+    def make_plan(name, cand):
+        kind, kw = CANDIDATES[cand]
+        s = systems[name]
+        t0 = time.perf_counter()
         p = sp.Plan(s.row_ptr, s.col_idx, s.val)
+        t1 = time.perf_counter()
+        p.rewrite(kind, **kw)
         t2 = time.perf_counter()
-        p.rewrite(kind, **pol)
-        t3 = time.perf_counter()
         p.upload()
-        t4 = time.perf_counter()
-        systems[name], plans[name] = s, p
-        host[name] = {"generate_s": t1 - t0, "analyse_s": t2 - t1, "rewrite_s": t3 - t2,
-                      "upload_s": t4 - t3}
-        if not args.no_plain:
-            plain[name] = sp.Plan(s.row_ptr, s.col_idx, s.val).upload()
-        bs[name] = torch.from_numpy(s.b).to(dev)
-        xs[name] = torch.empty_like(bs[name])
-        info = p.info()
-        log(f"[setup] {name}: n={info['n']} nnz={info['nnz']} levels {info['levels']} -> "
-            f"{info['levels_rw']} (stages {info['stages']}), entries {info['nnz']} -> "
-            f"{info['nnz_rw'] + info['nnz_m']}, tiles {info['tiles']}, host {host[name]}")
+        return p, {"analyse_s": t1 - t0, "rewrite_s": t2 - t1, "upload_s": time.perf_counter() - t2}
 
-    stream = torch.cuda.current_stream()
+    bs = {n: torch.from_numpy(systems[n].b).to(dev) for n in names}
+    xs = {n: torch.empty_like(bs[n]) for n in names}
 
+    def time_solves(p, n, reps):
+        p.solve(bs[n], xs[n])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            p.solve(bs[n], xs[n])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # ---- tuning leg
+    plans, chosen, tuning = {}, {}, {}
+    for n in names:
+        if args.no_tune:
+            chosen[n] = TUNED.get(n, "paper")
+            plans[n], h = make_plan(n, chosen[n])
+            host[n].update(h)
+            continue
+        best = None
+        tuning[n] = {}
+        for cand in CANDIDATES:
+            p, h = make_plan(n, cand)
+            ms = time_solves(p, n, 2)
+            st = p.check()
+            i = p.info()
+            tuning[n][cand] = {"ms": ms, "levels_rw": i["levels_rw"],
+                               "entries": i["nnz_rw"] + i["nnz_m"], "status": st}
+            log(f"[tune] {n} {cand}: {ms:.3f} ms, levels {i['levels']} -> {i['levels_rw']}, "
+                f"entries {i['nnz']} -> {i['nnz_rw'] + i['nnz_m']}, rewrite {h['rewrite_s']:.2f} s")
+            if st == 0 and (best is None or ms < best[0]):
+                if best is not None:
+                    best[1].close()
+                best = (ms, p, cand, h)
+            else:
+                p.close()
+        _, plans[n], chosen[n], h = best
+        host[n].update(h)
+
+    # ---- timed leg
     def run(plan_set, steps, tag):
-        ev = {n: [] for n in names}
         for _ in range(args.warmup):
             for n in names:
                 plan_set[n].solve(bs[n], xs[n])
         torch.cuda.synchronize()
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
+        ev = {n: [] for n in names}
         start.record(stream)
         for _ in range(steps):
             for n in names:
@@ -121,94 +202,78 @@ def main():
         total_ms = start.elapsed_time(end)
         per = {n: float(np.mean([a.elapsed_time(b) for a, b in ev[n]])) for n in names}
         status = {n: plan_set[n].check() for n in names}
-        errs = {}
-        for n in names:
-            s = systems[n]
-            ref = refs.setdefault(n, None)
-            if ref is None:
-                import oracle
-                ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
-                refs[n] = ref
-            errs[n] = errors(xs[n].cpu().numpy(), ref)
-        log(f"[{tag}] {steps} steps, {total_ms / steps:.3f} ms/step, per-solve ms "
-            f"{ {n: round(v, 4) for n, v in per.items()} }, (strict, floored) err {errs}, status {status}")
+        errs = {n: errors(xs[n].cpu().numpy(), refs[n]) if n in refs else None for n in names}
+        log(f"[{tag}] {steps} steps, {total_ms / steps:.3f} ms/step, per solve (ms) "
+            f"{ {n: round(v, 4) for n, v in per.items()} }, (strict, floored) error {errs}, "
+            f"status {status}")
         return total_ms, per, errs, status
 
-    refs = {}
-    log("[timed] rewritten plans")
-    total_ms, per, errs, status = run(plans, args.steps, "rewritten")
+    log("[timed] tuned plans")
+    total_ms, per, errs, status = run(plans, args.steps, "timed")
     plain_res = None
     if not args.no_plain:
-        ps = args.plain_steps or max(2, args.steps // 4)
-        log("[timed] plain level-set plans")
-        plain_res = run(plain, ps, "plain")
+        plain = {n: make_plan(n, "plain")[0] for n in names}
+        plain_res = run(plain, args.plain_steps, "plain")
 
     ms_per_step = total_ms / args.steps
-    solves = len(names)
-    value = solves * 1000.0 / ms_per_step
-    bytes_rw = {n: plans[n].info()["bytes_rw"] for n in names}
-    bytes_plain = {n: plans[n].info()["bytes"] for n in names}
-    kern_ms = sum(per.values())
-    achieved = sum(bytes_rw.values()) / (kern_ms * 1e-3) / 1e9
+    nsolve = len(names)
+    value = nsolve * 1000.0 / ms_per_step
     matrices = {}
     for n in names:
         i = plans[n].info()
         m = {
             "n": i["n"], "nnz": i["nnz"], "levels": i["levels"], "stages": i["stages"],
             "levels_rw": i["levels_rw"], "entries_rw": i["nnz_rw"] + i["nnz_m"],
-            "flops": i["flops"], "flops_rw": i["flops_rw"],
-            "ms_per_solve": per[n], "solves_per_s": 1000.0 / per[n],
-            "plan_gbps": bytes_rw[n] / (per[n] * 1e-3) / 1e9,
-            "effective_gbps": bytes_plain[n] / (per[n] * 1e-3) / 1e9,
-            "max_rel_err_strict": errs[n][0], "max_rel_err_floored": errs[n][1],
-            "device_status": status[n],
-            "policy": POLICIES.get(n), **{k: round(v, 3) for k, v in host[n].items()},
+            "flops": i["flops"], "flops_rw": i["flops_rw"], "bytes": i["bytes"],
+            "bytes_rw": i["bytes_rw"], "policy": chosen[n], "ms_per_solve": per[n],
+            "solves_per_s": 1000.0 / per[n],
+            "plan_gbps": i["bytes_rw"] / (per[n] * 1e-3) / 1e9,
+            "effective_gbps": i["bytes"] / (per[n] * 1e-3) / 1e9,
+            "us_per_level": 1000.0 * per[n] / max(1, i["levels_rw"]),
+            "device_status": status[n], **{k: round(v, 3) for k, v in host[n].items()},
         }
+        if errs[n] is not None:
+            m["max_rel_err_strict"], m["max_rel_err_floored"] = errs[n]
         if plain_res is not None:
             m["plain_ms_per_solve"] = plain_res[1][n]
-            m["plain_max_rel_err_floored"] = plain_res[2][n][1]
             m["speedup_vs_plain"] = plain_res[1][n] / per[n]
+            if plain_res[2][n] is not None:
+                m["plain_max_rel_err_floored"] = plain_res[2][n][1]
+        if n in tuning:
+            m["tuning_ms"] = {c: round(v["ms"], 4) for c, v in tuning[n].items()}
         matrices[n] = m
-    ok = all(e[1] <= TOL for e in errs.values()) and not any(status.values())
-    if plain_res is not None:
-        ok = ok and all(e[1] <= TOL for e in plain_res[2].values()) and not any(plain_res[3].values())
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        cores = 1
-        t_total, count = 0.0, 0
-        t0 = time.perf_counter()
-        while t_total < args.cpu_seconds:
-            for n in names:
-                s = systems[n]
-                oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
-                count += 1
-            t_total = time.perf_counter() - t0
-        cpu = {"value": count / t_total, "unit": "solves/s", "cores": cores, "kind": "oracle",
-               "sample": f"serial FP64 oracle forward substitution, the same {solves} systems "
-                         f"cycled {count // solves} times ({t_total:.1f} s)"}
-
+    parity = None
+    if refs:
+        parity = all(e[1] <= TOL for e in errs.values()) and not any(status.values())
+        if plain_res is not None:
+            parity = parity and all(e[1] <= TOL for e in plain_res[2].values()) \
+                and not any(plain_res[3].values())
+    # roofline of the solve kernel: algorithmic bytes of the rewritten plans
+    # over the time of their solves (fill kernel included: it is part of
+    # every solve), against the 8 TB/s HBM peak
+    kern_ms = sum(per.values())
+    achieved = sum(plans[n].info()["bytes_rw"] for n in names) / (kern_ms * 1e-3) / 1e9
     out = {
         "metric": "SpTRSV solves/s + achieved HBM GB/s vs plain level-set, rel err <=1e-10",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "stencil3d_128 + banded_1m + powerlaw_4m, FP64 CSR, 1 RHS"
-                   if args.workload == "large" else "stencil2d_100, FP64 CSR, 1 RHS",
-                   "solves_per_step": solves},
+        "config": {"workload": ("stencil3d_128 + banded_1m + powerlaw_4m, FP64 CSR int32, 1 RHS"
+                                if args.workload == "large" else "stencil2d_100, FP64 CSR int32, 1 RHS"),
+                   "solves_per_step": nsolve},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
-        "parity_ok": ok,
+        "parity_ok": parity,
         "plain_levelset": None if plain_res is None else {
-            "solves_per_s": solves * 1000.0 * (args.plain_steps or max(2, args.steps // 4)) / plain_res[0],
-            "speedup_of_rewrite": (plain_res[0] / (args.plain_steps or max(2, args.steps // 4))) / ms_per_step,
+            "solves_per_s": nsolve * 1000.0 * args.plain_steps / plain_res[0],
+            "speedup_of_rewrite": (plain_res[0] / args.plain_steps) / ms_per_step,
         },
         "matrices": matrices,
     }
     print(json.dumps(out), flush=True)
-    if not ok:
+    if parity is False:
         sys.exit(1)
 
 

@@ -84,6 +84,16 @@ __device__ inline unsigned long long load_agent(const double *p) {
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// First attempt at a gather: an ordinary (cached) load.  Stream order makes
+// the fill of x visible to this kernel and no cache holds x lines from before
+// it, so within the solve a cached copy of x_k is either the not-ready
+// pattern or the final value: a stale pattern only sends the lane to the
+// device-scope poll, never yields a wrong value.  It lets repeated gathers
+// of a published value hit in L2 instead of going to memory each time.
+__device__ inline unsigned long long load_cached(const double *p) {
+    return *reinterpret_cast<const unsigned long long *>(p);
+}
+
 // Bits of x[k] once it is published (a quiet NaN if the wait gave up).
 // Only reached behind a wave-uniform branch (see resolve_pending), so the
 // call and the waits it implies stay off the path where nothing is pending.
@@ -121,15 +131,45 @@ __device__ inline bool pending(const SolveArgs &a, int32_t k, unsigned long long
 // Waits for every gathered x-term that was not yet published.  The test is a
 // wave-wide vote: with a lane-divergent branch the compiler would drain every
 // load in flight (the prefetches too) before it on all paths.
-template <int kN>
+//   kElect (wide tiles): while terms are pending, one elected lane polls one
+//     of its pending terms; once that value appears every lane re-reads its
+//     pending terms once.  The rows a wide tile waits on finish at about the
+//     same time, so this costs little latency and keeps the polling traffic
+//     to one lane per waiting wave (waves run ahead of the frontier).
+//   otherwise (segments, which rarely wait and then on a single row just
+//     produced by another wave): every pending lane polls its own term.
+template <int kN, bool kElect>
 __device__ inline void resolve_pending(const SolveArgs &a, const int32_t *col, unsigned long long *g) {
     bool any = false;
 #pragma unroll
     for (int c = 0; c < kN; ++c) any |= pending(a, col[c], g[c]);
-    if (__ballot(any)) {
+    unsigned long long mask = __ballot(any);
+    if (!kElect) {
+        if (mask) {
 #pragma unroll
-        for (int c = 0; c < kN; ++c)
-            if (pending(a, col[c], g[c])) g[c] = wait_slow(a.x, col[c], a.ws, a.wait_limit);
+            for (int c = 0; c < kN; ++c)
+                if (pending(a, col[c], g[c])) g[c] = wait_slow(a.x, col[c], a.ws, a.wait_limit);
+        }
+        return;
+    }
+    while (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        if ((int)(threadIdx.x & 63) == leader) {
+            bool done = false;
+#pragma unroll
+            for (int c = 0; c < kN; ++c)
+                if (!done && pending(a, col[c], g[c])) {
+                    g[c] = wait_slow(a.x, col[c], a.ws, a.wait_limit);
+                    done = true;
+                }
+        }
+        any = false;
+#pragma unroll
+        for (int c = 0; c < kN; ++c) {
+            if (pending(a, col[c], g[c])) g[c] = load_agent(a.x + col[c]);
+            any |= pending(a, col[c], g[c]);
+        }
+        mask = __ballot(any);
     }
 }
 
@@ -242,7 +282,7 @@ __device__ inline void seg_load(const SolveArgs &a, long long st, int lane, SegS
 
 __device__ inline void seg_gather(const SolveArgs &a, SegSlot &S) {
 #pragma unroll
-    for (int c = 0; c < kSegChunks; ++c) S.g[c] = load_agent(gather_addr(a, seg_col(S, c)));
+    for (int c = 0; c < kSegChunks; ++c) S.g[c] = load_cached(gather_addr(a, seg_col(S, c)));
     S.bi = a.b[S.rm.x >= 0 ? S.rm.x : 0];
 }
 
@@ -250,7 +290,7 @@ __device__ inline void seg_finish(const SolveArgs &a, SegSlot &S, double *ring) 
     int32_t col[kSegChunks];
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) col[c] = seg_col(S, c);
-    resolve_pending<kSegChunks>(a, col, S.g);
+    resolve_pending<kSegChunks, false>(a, col, S.g);
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) {
@@ -333,7 +373,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs a) {
 #pragma unroll
         for (int c = 0; c < kRegChunks; ++c) {
             col[c] = tile_col(cur, c, lane);
-            g[c] = load_agent(gather_addr(a, col[c]));
+            g[c] = load_cached(gather_addr(a, col[c]));
         }
         const bool lead = tile_lead(cur.d, lane);
         const double bi = a.b[lead ? cur.row : 0];
@@ -347,7 +387,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs a) {
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         // 3. wait for the gathers, accumulate
-        resolve_pending<kRegChunks>(a, col, g);
+        resolve_pending<kRegChunks, true>(a, col, g);
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < kRegChunks; ++c) acc = fma(tile_val(cur, c, lane), term_value(col[c], g[c]), acc);
@@ -358,7 +398,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs a) {
                 for (int c = kRegChunks; c < cur.d.z; ++c) {
                     const int32_t k = a.tcol[base + (size_t)c * 64];
                     const double v = a.tval[base + (size_t)c * 64];
-                    unsigned long long gv = load_agent(gather_addr(a, k));
+                    unsigned long long gv = load_cached(gather_addr(a, k));
                     if (pending(a, k, gv)) gv = wait_slow(a.x, k, a.ws, a.wait_limit);
                     acc = fma(v, term_value(k, gv), acc);
                 }
