@@ -108,6 +108,19 @@ void sptrsv_policy_default(sptrsv_policy *p);
 sptrsv_status sptrsv_analyse(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                              const double *val, sptrsv_plan *out);
 
+/* Analysis of an UPPER-triangular U (CSR, columns strictly increasing, the
+ * diagonal FIRST in each row, non-zero), for the backward substitution
+ * U x = b that follows the forward solve in LU / incomplete-LU
+ * preconditioners.  The plan holds U with its index order reversed (row i of
+ * the plan is row n-1-i of U), which is lower triangular, so rewriting
+ * (Sec. III works on the dependency graph, whatever its orientation) and
+ * solving are unchanged; sptrsv_solve takes b and x in U's own order.  The
+ * introspection calls (levels, stages, schedule, export) report the reversed
+ * matrix.  Errors as sptrsv_analyse (CSR also for an entry below the
+ * diagonal). */
+sptrsv_status sptrsv_analyse_upper(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                   const double *val, sptrsv_plan *out);
+
 /* Equation rewriting (Sec. III) under *policy, always starting again from
  * the analysed L (so repeated calls do not compound).  Builds the rewritten
  * rows L' (x-terms plus the unchanged diagonal), the right-hand-side

@@ -50,6 +50,7 @@ def _load():
         sig = {
             "oracle_solve": (None, [I, P, P, P, P, P]),
             "oracle_solve_ld": (None, [I, P, P, P, P, P]),
+            "oracle_solve_upper": (None, [I, P, P, P, P, P]),
             "oracle_levels": (I, [I, P, P, P]),
             "oracle_level_sets": (None, [I, P, I, P, P]),
             "oracle_select_stages": (I, [I, P, P, P, I, I, I, I, D, L, P, I, P, P]),
@@ -89,6 +90,20 @@ def solve(row_ptr, col_idx, val, b) -> np.ndarray:
     b = np.ascontiguousarray(b)
     x = np.empty(n, dtype=np.float64)
     _load().oracle_solve(n, _p(rp), _p(ci), _p(v), _p(b), _p(x))
+    return x
+
+
+def solve_upper(row_ptr, col_idx, val, b) -> np.ndarray:
+    """Backward substitution in FP64 for an upper-triangular CSR matrix
+    (diagonal first in each row).  ``b`` of shape (n,) or (n, k)."""
+    rp, ci, v = _csr(row_ptr, col_idx, val)
+    n = rp.size - 1
+    b = np.asarray(b, dtype=np.float64)
+    if b.ndim == 2:
+        return np.stack([solve_upper(rp, ci, v, b[:, c]) for c in range(b.shape[1])], axis=1)
+    b = np.ascontiguousarray(b)
+    x = np.empty(n, dtype=np.float64)
+    _load().oracle_solve_upper(n, _p(rp), _p(ci), _p(v), _p(b), _p(x))
     return x
 
 

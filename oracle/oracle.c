@@ -78,6 +78,28 @@ void oracle_solve_ld(int n, const int *row_ptr, const int *col_idx,
     free(xl);
 }
 
+/* Backward substitution for an upper-triangular U (diagonal first in each
+ * row): for i = n-1 down to 0, x_i = (b_i - sum_{j>i} U_ij x_j) / U_ii, the
+ * partial sum taken in ascending column order.  This is the triangular solve
+ * that follows the forward one in LU / ILU preconditioners; the rewriting of
+ * Sec. III applies to its dependency DAG unchanged (Sec. III notes the method
+ * works on the dependency graph itself). */
+void oracle_solve_upper(int n, const int *row_ptr, const int *col_idx,
+                        const double *val, const double *b, double *x)
+{
+    for (int i = n - 1; i >= 0; --i) {
+        double s = 0.0, d = 0.0;
+        for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            int j = col_idx[p];
+            if (j > i)
+                s = s + val[p] * x[j];
+            else
+                d = val[p];
+        }
+        x[i] = (b[i] - s) / d;
+    }
+}
+
 /* --------------------------------------------------------------- levels -- */
 
 /* Level of every row in DAG_L (Sec. II; level sets as in the level-set

@@ -73,6 +73,7 @@ def load():
     sig = {
         "sptrsv_policy_default": (None, [P]),
         "sptrsv_analyse": (S, [I32, P, P, P, P]),
+        "sptrsv_analyse_upper": (S, [I32, P, P, P, P]),
         "sptrsv_rewrite": (S, [P, P]),
         "sptrsv_device_bytes": (S, [P, P]),
         "sptrsv_upload": (S, [P, P, ctypes.c_size_t, P]),
@@ -128,16 +129,18 @@ def make_policy(kind: str = "threshold", max_width: int = 4, max_depth: int = 64
 
 
 class Plan:
-    """Analysis, rewrite and solve of one lower-triangular CSR matrix."""
+    """Analysis, rewrite and solve of one triangular CSR matrix (lower by
+    default; ``upper=True`` for backward substitution, diagonal first)."""
 
-    def __init__(self, row_ptr, col_idx, val):
+    def __init__(self, row_ptr, col_idx, val, upper: bool = False):
         lib = load()
         self._rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         v = np.ascontiguousarray(val, dtype=np.float64)
         n = self._rp.size - 1
         h = ctypes.c_void_p()
-        _check(lib.sptrsv_analyse(n, _ptr(self._rp), _ptr(ci), _ptr(v), ctypes.byref(h)))
+        fn = lib.sptrsv_analyse_upper if upper else lib.sptrsv_analyse
+        _check(fn(n, _ptr(self._rp), _ptr(ci), _ptr(v), ctypes.byref(h)))
         self._h = h
         self.n = n
         self._buf = None

@@ -65,4 +65,46 @@ void analyse(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const dou
     level_sets(n, p.level.data(), p.nlev, p.level_ptr, p.level_rows);
 }
 
+// Upper-triangular U (diagonal first in each row): validate, then hold it with
+// the index order reversed, U'[n-1-i][n-1-j] = U[i][j], which is lower
+// triangular with the diagonal last.  Backward substitution on U is forward
+// substitution on U' with b and x reversed; the device image maps indices back.
+void analyse_upper(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const double *val) {
+    if (n < 0) fail(SPTRSV_ERR_ARG, "n < 0");
+    if (n > 0) {
+        if (!rp || !ci || !val) fail(SPTRSV_ERR_ARG, "null CSR array");
+        if (rp[0] != 0) fail(SPTRSV_ERR_CSR, "row_ptr[0] != 0");
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t b = rp[i], e = rp[i + 1];
+            if (e < b) fail(SPTRSV_ERR_CSR, "row_ptr decreases at row " + std::to_string(i));
+            if (e == b) fail(SPTRSV_ERR_DIAG, "row " + std::to_string(i) + " is empty (no diagonal)");
+            int32_t prev = -1;
+            for (int32_t q = b; q < e; ++q) {
+                const int32_t c = ci[q];
+                if (c < 0 || c >= n) fail(SPTRSV_ERR_CSR, "column out of range in row " + std::to_string(i));
+                if (c <= prev) fail(SPTRSV_ERR_CSR, "columns not strictly increasing in row " + std::to_string(i));
+                if (c < i) fail(SPTRSV_ERR_CSR, "entry below the diagonal in row " + std::to_string(i));
+                prev = c;
+            }
+            if (ci[b] != i) fail(SPTRSV_ERR_DIAG, "row " + std::to_string(i) + " has no diagonal");
+            if (val[b] == 0.0) fail(SPTRSV_ERR_DIAG, "zero diagonal in row " + std::to_string(i));
+        }
+    }
+    const size_t nnz = n ? (size_t)rp[n] : 0;
+    std::vector<int32_t> rrp((size_t)n + 1, 0), rci(nnz);
+    std::vector<double> rval(nnz);
+    size_t q = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        const int32_t i = n - 1 - r;
+        for (int32_t t = rp[i + 1] - 1; t >= rp[i]; --t) {
+            rci[q] = n - 1 - ci[t];
+            rval[q] = val[t];
+            ++q;
+        }
+        rrp[(size_t)r + 1] = (int32_t)q;
+    }
+    analyse(p, n, rrp.data(), rci.data(), rval.data());
+    p.upper = true;
+}
+
 }  // namespace sptrsv

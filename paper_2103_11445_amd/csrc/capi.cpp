@@ -96,6 +96,26 @@ sptrsv_status sptrsv_analyse(int32_t n, const int32_t *row_ptr, const int32_t *c
     });
 }
 
+sptrsv_status sptrsv_analyse_upper(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                   const double *val, sptrsv_plan *out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> sptrsv_status {
+        if (!out) return set_err(SPTRSV_ERR_ARG, "out is NULL");
+        sptrsv_plan p = new sptrsv_plan_s();
+        try {
+            sptrsv::analyse_upper(*p, n, row_ptr, col_idx, val);
+            sptrsv_policy none{};
+            none.kind = SPTRSV_POLICY_NONE;
+            sptrsv::rewrite(*p, none);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return SPTRSV_OK;
+    });
+}
+
 sptrsv_status sptrsv_rewrite(sptrsv_plan plan, const sptrsv_policy *policy) {
     return guarded([&]() -> sptrsv_status {
         if (!plan || !policy) return set_err(SPTRSV_ERR_ARG, "null argument");

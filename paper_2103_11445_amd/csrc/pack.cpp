@@ -202,19 +202,21 @@ void pack(Plan &p) {
     std::fill(tcol, tcol + nchunks * 64, kPad);
     std::fill(scol, scol + nst * kSegChunks * 64, kPad);
     for (int64_t q = 0; q < nst * 64; ++q) srow[2 * q] = -1;
+    // the device image speaks the caller's indices (reversed for upper input)
+    auto orig = [&](int32_t i) { return p.upper ? n - 1 - i : i; };
     for (int32_t s = 0; s < n; ++s) {
         const int32_t i = slot_row[(size_t)s];
-        trow[s] = i;
+        trow[s] = orig(i);
         tdiag[s] = p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1];
     }
 
     // terms of row i for a tile with 2^lg lanes per row, written through put(col, val)
     auto row_terms = [&](int32_t i, int32_t seg, int32_t first_slot_of_tile, auto &&put) {
         for (int64_t q = p.m_ptr[(size_t)i]; q < p.m_ptr[(size_t)i + 1]; ++q)
-            put(~p.m_col[(size_t)q], p.m_val[(size_t)q]);
+            put(~orig(p.m_col[(size_t)q]), p.m_val[(size_t)q]);
         for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q) {
             const int32_t k = p.lp_col[(size_t)q];
-            int32_t col = k;
+            int32_t col = orig(k);
             if (seg >= 0) {
                 const int32_t sk = slot_of_row[(size_t)k];
                 if (seg_of_slot[(size_t)sk] == seg && first_slot_of_tile - sk <= kRing)
@@ -241,7 +243,7 @@ void pack(Plan &p) {
                     const int32_t s = T.row_off + r;
                     const int32_t i = slot_row[(size_t)s];
                     const int64_t lead = st * 64 + r * g;
-                    srow[2 * lead] = i;
+                    srow[2 * lead] = orig(i);
                     srow[2 * lead + 1] = T.lg | (((s - seg_first[(size_t)sid]) & (kRing - 1)) << 8);
                     sdiag[lead] = tdiag[s];
                     int64_t t_ = 0;

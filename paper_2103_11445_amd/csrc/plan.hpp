@@ -51,8 +51,12 @@ struct Workspace {
 static_assert(sizeof(Workspace) == 64, "workspace block is one cache line");
 
 struct Plan {
-    // ---- analysed matrix (Sec. II / IV)
+    // ---- analysed matrix (Sec. II / IV); for an upper-triangular input the
+    // matrix is held with its index order reversed (row i <-> n-1-i), which
+    // makes it lower triangular, and only the device image uses the caller's
+    // indices
     int32_t n = 0;
+    bool upper = false;
     std::vector<int32_t> rp, ci;
     std::vector<double> val;
     std::vector<int32_t> level;  // level of each row of L
@@ -91,6 +95,7 @@ struct Plan {
 // analyse.cpp
 void validate_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
 void analyse(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
+void analyse_upper(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
 void level_sets(int32_t n, const int32_t *level, int32_t nlev, std::vector<int32_t> &ptr,
                 std::vector<int32_t> &rows);
 

@@ -210,3 +210,54 @@ def test_null_and_state_errors_without_gpu(sp):
     assert sp.STATUS[lib.sptrsv_check(plan._h, None, ctypes.byref(st))] == "ERR_STATE"
     assert sp.STATUS[lib.sptrsv_upload(plan._h, None, 0, None)] == "ERR_ARG"
     lib.sptrsv_plan_destroy(None)  # ignored
+
+
+# ------------------------------------------ upper-triangular input (U x = b) --
+
+def _reversed_lower(s):
+    """The lower-triangular matrix obtained by reversing the index order of an
+    upper-triangular system, built independently of the library."""
+    n = s.n
+    rows = []
+    for r in range(n):
+        i = n - 1 - r
+        seg = slice(s.row_ptr[i], s.row_ptr[i + 1])
+        rows.append((n - 1 - s.col_idx[seg][::-1], s.val[seg][::-1]))
+    rp = np.concatenate([[0], np.cumsum([len(c) for c, _ in rows])]).astype(np.int32)
+    ci = np.concatenate([c for c, _ in rows]).astype(np.int32)
+    v = np.concatenate([x for _, x in rows])
+    return rp, ci, v
+
+
+@pytest.mark.parametrize("make", [lambda: wl.stencil2d(40, seed=2), lambda: wl.powerlaw(30000, 700, seed=5),
+                                  lambda: wl.banded(3000, 200, 8, 24, seed=4)])
+def test_upper_plan_is_the_reversed_lower_plan(sp, make):
+    U = wl.transpose(make())
+    rp, ci, v = _reversed_lower(U)
+    pol = {"kind": "threshold", "max_width": 10**9, "max_depth": 4, "max_fill": 10.0}
+    plan = sp.Plan(U.row_ptr, U.col_idx, U.val, upper=True)
+    plan.rewrite("threshold", max_width=10**9, max_depth=4, max_fill=10.0)
+    o = oracle.plan(rp, ci, v, pol)
+    assert np.array_equal(plan.levels(0), o["level"])
+    lp, m = plan.export()
+    for a, b in zip(lp + m, o["lp"] + o["m"]):
+        assert np.array_equal(a, b)
+
+
+def test_upper_errors(sp):
+    lib = sp.load()
+    h = ctypes.c_void_p()
+
+    def st(n, rp, ci, v):
+        rp = np.ascontiguousarray(rp, np.int32)
+        ci = np.ascontiguousarray(ci, np.int32)
+        v = np.ascontiguousarray(v, np.float64)
+        r = lib.sptrsv_analyse_upper(n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, ctypes.byref(h))
+        if r == 0:
+            lib.sptrsv_plan_destroy(h)
+        return sp.STATUS[r]
+
+    assert st(2, [0, 2, 3], [0, 1, 1], [2.0, -1.0, 3.0]) == "OK"
+    assert st(2, [0, 2, 3], [0, 1, 0], [2.0, -1.0, 3.0]) == "ERR_CSR"   # below the diagonal
+    assert st(2, [0, 1, 2], [1, 1], [2.0, 3.0]) == "ERR_DIAG"           # row 0 has no diagonal
+    assert st(2, [0, 2, 3], [0, 1, 1], [0.0, -1.0, 3.0]) == "ERR_DIAG"  # zero diagonal

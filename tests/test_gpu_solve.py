@@ -144,3 +144,18 @@ def test_solve_state_errors(torch, sp):
     with pytest.raises(sp.SptrsvError) as e:
         plan.solve(b)
     assert e.value.status == "ERR_STATE"
+
+
+@pytest.mark.parametrize("make", [lambda: wl.stencil3d(20, seed=31), lambda: wl.banded(8000, 200, 8, 24, seed=32),
+                                  lambda: wl.powerlaw(60000, 1500, seed=33)])
+@pytest.mark.parametrize("kind,kw", POLICIES)
+def test_upper_backward_substitution(torch, sp, make, kind, kw):
+    """U x = b with U = L^T (backward substitution) against the oracle's
+    backward substitution."""
+    U = wl.transpose(make())
+    ref = oracle.solve_upper(U.row_ptr, U.col_idx, U.val, U.b)
+    plan = sp.Plan(U.row_ptr, U.col_idx, U.val, upper=True).rewrite(kind, **kw).upload()
+    b = torch.from_numpy(U.b).cuda()
+    x = plan.solve(b)
+    assert plan.check() == 0
+    assert relerr(x.cpu().numpy(), ref) <= TOL

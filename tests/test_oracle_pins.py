@@ -339,3 +339,28 @@ def test_long_double_is_closer_to_exact():
 def test_flops_definition():
     s = wl.stencil2d(10, seed=0)
     assert oracle.flops(s.row_ptr) == 2 * (s.nnz - s.n) + s.n
+
+
+# ------------------------------------------ backward substitution (U x = b) --
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_solve_upper_exhaustive(n):
+    """Backward substitution against exact Gauss-Jordan on the transposes of
+    every strictly-lower pattern."""
+    for t, pairs in enumerate(all_lower_patterns(n)):
+        s = wl.transpose(wl.from_pairs(n, pairs, seed=t))
+        x = oracle.solve_upper(s.row_ptr, s.col_idx, s.val, s.b)
+        ex = exact_solve(s.row_ptr, s.col_idx, s.val, s.b)
+        scale = max(abs(e) for e in ex)
+        for i in range(n):
+            assert abs(Fraction(float(x[i])) - ex[i]) <= scale * Fraction(1e-14), (pairs, i)
+
+
+def test_solve_upper_suffix_sums():
+    """Unit upper bidiagonal (1 on the diagonal, -1 above) gives suffix sums."""
+    rng = np.random.default_rng(5)
+    n = 3000
+    rp, ci, v, b = _unit_bidiagonal(n, rng)
+    U = wl.transpose(wl.System("bd", rp, ci, v, b))
+    x = oracle.solve_upper(U.row_ptr, U.col_idx, U.val, b)
+    assert np.array_equal(x, np.cumsum(b[::-1])[::-1])

@@ -38,7 +38,7 @@ import numpy as np
 
 __all__ = [
     "System", "assemble", "stencil2d", "stencil3d", "banded", "powerlaw",
-    "random_lower", "bidiagonal", "diagonal", "from_pairs", "config",
+    "random_lower", "bidiagonal", "diagonal", "from_pairs", "transpose", "config",
     "CONFIGS", "rhs",
 ]
 
@@ -248,6 +248,19 @@ def diagonal(n: int, seed: int = 0) -> System:
     """No off-diagonal entries at all."""
     e = np.zeros(0, dtype=np.int64)
     return assemble(f"diagonal_{n}", n, e, e, np.random.default_rng(seed))
+
+
+def transpose(s: System, name: str | None = None) -> System:
+    """The upper-triangular transpose U = L^T of a lower system (CSR with the
+    diagonal first in each row), keeping its right-hand sides."""
+    n = s.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(s.row_ptr))
+    order = np.lexsort((rows, s.col_idx.astype(np.int64)))  # by column, then row
+    t_rows = s.col_idx[order].astype(np.int64)
+    t_cols = rows[order].astype(np.int32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(t_rows, minlength=n), out=row_ptr[1:])
+    return System(name or s.name + "_T", row_ptr.astype(np.int32), t_cols, s.val[order], s.b)
 
 
 # ------------------------------------------------------ named workloads --
