@@ -121,6 +121,21 @@ sptrsv_status sptrsv_analyse(int32_t n, const int32_t *row_ptr, const int32_t *c
 sptrsv_status sptrsv_analyse_upper(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                                    const double *val, sptrsv_plan *out);
 
+/* Analysis of a batch: `count` lower-triangular systems (n[j], row_ptr[j],
+ * col_idx[j], val[j] as for sptrsv_analyse, host, read during the call), the
+ * j-th with k[j] >= 1 right-hand sides.  The plan is the block-diagonal union
+ * of k[j] copies of each matrix, so one solve (one launch, the levels of all
+ * systems interleaved) handles every system and every right-hand side.
+ * sptrsv_solve then takes b and x as the concatenation, in order j = 0..,
+ * of row-major n[j] x k[j] blocks (entry (i, c) of system j at
+ * base_j + i*k[j] + c, base_j = sum_{j' < j} n[j'] k[j']).  Introspection
+ * reports the union (copy c of system j occupies union rows
+ * base_j + c*n[j] .. + n[j]).  Errors: as sptrsv_analyse (message names the
+ * system), ARG (k < 1, null arrays), OVERFLOW (union beyond int32). */
+sptrsv_status sptrsv_analyse_batch(int32_t count, const int32_t *n, const int32_t *const *row_ptr,
+                                   const int32_t *const *col_idx, const double *const *val,
+                                   const int32_t *k, sptrsv_plan *out);
+
 /* Equation rewriting (Sec. III) under *policy, always starting again from
  * the analysed L (so repeated calls do not compound).  Builds the rewritten
  * rows L' (x-terms plus the unchanged diagonal), the right-hand-side
@@ -149,6 +164,13 @@ sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void 
  * that exceeds the wait limit is reported by sptrsv_check.  Errors: ARG,
  * STATE (not uploaded or stale), HIP. */
 sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *stream);
+
+/* As sptrsv_solve, through a HIP graph: the fill and solve launches are
+ * captured once (on a stream the plan owns) for these b and x and replayed
+ * on `stream` by later calls with the same pointers (a different b, x, launch
+ * shape, rewrite or upload captures again).  For callers that replay one
+ * solve many times.  Errors: as sptrsv_solve, HIP (capture refused). */
+sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, void *stream);
 
 /* Waits for stream, then reads and clears the plan's device status word:
  * *device_status = 0 if every solve since the last check completed normally,

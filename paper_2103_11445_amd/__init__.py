@@ -74,6 +74,8 @@ def load():
         "sptrsv_policy_default": (None, [P]),
         "sptrsv_analyse": (S, [I32, P, P, P, P]),
         "sptrsv_analyse_upper": (S, [I32, P, P, P, P]),
+        "sptrsv_analyse_batch": (S, [I32, P, P, P, P, P, P]),
+        "sptrsv_solve_graph": (S, [P, P, P, P]),
         "sptrsv_rewrite": (S, [P, P]),
         "sptrsv_device_bytes": (S, [P, P]),
         "sptrsv_upload": (S, [P, P, ctypes.c_size_t, P]),
@@ -131,6 +133,30 @@ def make_policy(kind: str = "threshold", max_width: int = 4, max_depth: int = 64
 class Plan:
     """Analysis, rewrite and solve of one triangular CSR matrix (lower by
     default; ``upper=True`` for backward substitution, diagonal first)."""
+
+    @classmethod
+    def batch(cls, systems, k=None) -> "Plan":
+        """One plan for many lower-triangular systems, ``systems`` a list of
+        (row_ptr, col_idx, val) and ``k`` the right-hand sides of each (default
+        1).  Solve with the concatenation of row-major n_j x k_j blocks."""
+        lib = load()
+        count = len(systems)
+        keep = [(np.ascontiguousarray(r, np.int32), np.ascontiguousarray(c, np.int32),
+                 np.ascontiguousarray(v, np.float64)) for r, c, v in systems]
+        ns = np.array([r.size - 1 for r, _, _ in keep], dtype=np.int32)
+        ks = np.ascontiguousarray(np.ones(count, np.int32) if k is None else k, dtype=np.int32)
+        ptrs = [(ctypes.c_void_p * max(count, 1))(*[a.ctypes.data for a in col]) for col in zip(*keep)] \
+            if count else [(ctypes.c_void_p * 1)() for _ in range(3)]
+        h = ctypes.c_void_p()
+        _check(lib.sptrsv_analyse_batch(count, _ptr(ns), ctypes.cast(ptrs[0], ctypes.c_void_p),
+                                        ctypes.cast(ptrs[1], ctypes.c_void_p),
+                                        ctypes.cast(ptrs[2], ctypes.c_void_p), _ptr(ks), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.n = int(np.sum(ns.astype(np.int64) * ks))
+        self._buf = None
+        self._rp = None
+        return self
 
     def __init__(self, row_ptr, col_idx, val, upper: bool = False):
         lib = load()
@@ -210,6 +236,14 @@ class Plan:
         if x is None:
             x = torch.empty_like(b)
         _check(load().sptrsv_solve(self._h, _ptr(b), _ptr(x), _stream(stream)))
+        return x
+
+    def solve_graph(self, b, x=None, stream=None):
+        """As :meth:`solve`, replaying a captured HIP graph for these b, x."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().sptrsv_solve_graph(self._h, _ptr(b), _ptr(x), _stream(stream)))
         return x
 
     def check(self, stream=None) -> int:

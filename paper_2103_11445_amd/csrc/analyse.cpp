@@ -1,6 +1,7 @@
 // analyse.cpp -- matrix analysis (arXiv:2103.11445, Sec. IV): validate and
 // copy L, build DAG_L's level of every row and the level sets (Sec. II).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -105,6 +106,53 @@ void analyse_upper(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, con
     }
     analyse(p, n, rrp.data(), rci.data(), rval.data());
     p.upper = true;
+}
+
+// Many systems at once: matrix j (n_j rows) with k_j right-hand sides becomes
+// k_j copies of its block on the diagonal of one lower-triangular union, so a
+// single plan (and a single launch) solves all of them.  Copy c of block j,
+// row i, is union row base_j + c*n_j + i and lives at base_j + i*k_j + c in
+// the concatenation of the callers' row-major n_j x k_j blocks.
+void analyse_batch(Plan &p, int32_t count, const int32_t *n, const int32_t *const *rp,
+                   const int32_t *const *ci, const double *const *val, const int32_t *k) {
+    if (count < 0) fail(SPTRSV_ERR_ARG, "count < 0");
+    if (count > 0 && (!n || !rp || !ci || !val || !k)) fail(SPTRSV_ERR_ARG, "null batch array");
+    int64_t rows = 0, nnz = 0;
+    for (int32_t j = 0; j < count; ++j) {
+        if (k[j] < 1) fail(SPTRSV_ERR_ARG, "k < 1 for system " + std::to_string(j));
+        try {
+            validate_csr(n[j], rp[j], ci[j], val[j]);
+        } catch (Error &e) {
+            e.msg = "system " + std::to_string(j) + ": " + e.msg;
+            throw;
+        }
+        rows += (int64_t)n[j] * k[j];
+        nnz += (int64_t)(n[j] ? rp[j][n[j]] : 0) * k[j];
+    }
+    if (rows > (int64_t)INT32_MAX - kRing || nnz > (int64_t)INT32_MAX)
+        fail(SPTRSV_ERR_OVERFLOW, "batch too large for int32 indexing");
+    std::vector<int32_t> urp((size_t)rows + 1, 0), uci((size_t)nnz);
+    std::vector<double> uval((size_t)nnz);
+    std::vector<int32_t> index((size_t)rows);
+    int64_t r = 0, q = 0, base = 0;
+    for (int32_t j = 0; j < count; ++j) {
+        for (int32_t c = 0; c < k[j]; ++c) {
+            const int64_t off = base + (int64_t)c * n[j];
+            for (int32_t i = 0; i < n[j]; ++i) {
+                for (int32_t t = rp[j][i]; t < rp[j][i + 1]; ++t) {
+                    uci[(size_t)q] = (int32_t)(off + ci[j][t]);
+                    uval[(size_t)q] = val[j][t];
+                    ++q;
+                }
+                index[(size_t)r] = (int32_t)(base + (int64_t)i * k[j] + c);
+                urp[(size_t)++r] = (int32_t)q;
+            }
+        }
+        base += (int64_t)n[j] * k[j];
+    }
+    analyse(p, (int32_t)rows, urp.data(), uci.data(), uval.data());
+    p.dev_index = std::move(index);
+    p.batch_count = count;
 }
 
 }  // namespace sptrsv

@@ -16,6 +16,19 @@
 struct sptrsv_plan_s : sptrsv::Plan {};
 
 namespace {
+void drop_graph(sptrsv::Plan &p) {
+    if (p.graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(p.graph_exec));
+    p.graph_exec = nullptr;
+    p.graph_b = p.graph_x = nullptr;
+}
+}  // namespace
+
+sptrsv::Plan::~Plan() {
+    drop_graph(*this);
+    if (capture_stream) hipStreamDestroy(static_cast<hipStream_t>(capture_stream));
+}
+
+namespace {
 thread_local std::string g_err;
 
 sptrsv_status set_err(sptrsv_status s, const std::string &m) {
@@ -116,11 +129,33 @@ sptrsv_status sptrsv_analyse_upper(int32_t n, const int32_t *row_ptr, const int3
     });
 }
 
+sptrsv_status sptrsv_analyse_batch(int32_t count, const int32_t *n, const int32_t *const *row_ptr,
+                                   const int32_t *const *col_idx, const double *const *val,
+                                   const int32_t *k, sptrsv_plan *out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> sptrsv_status {
+        if (!out) return set_err(SPTRSV_ERR_ARG, "out is NULL");
+        sptrsv_plan p = new sptrsv_plan_s();
+        try {
+            sptrsv::analyse_batch(*p, count, n, row_ptr, col_idx, val, k);
+            sptrsv_policy none{};
+            none.kind = SPTRSV_POLICY_NONE;
+            sptrsv::rewrite(*p, none);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return SPTRSV_OK;
+    });
+}
+
 sptrsv_status sptrsv_rewrite(sptrsv_plan plan, const sptrsv_policy *policy) {
     return guarded([&]() -> sptrsv_status {
         if (!plan || !policy) return set_err(SPTRSV_ERR_ARG, "null argument");
         sptrsv::validate_policy(*policy);
         plan->uploaded = false;
+        drop_graph(*plan);
         try {
             sptrsv::rewrite(*plan, *policy);
         } catch (...) {
@@ -159,6 +194,7 @@ sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void 
         if (e != hipSuccess) return hip_err(e, "hipMemcpyAsync");
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+        drop_graph(*plan);
         plan->dev = dev_buf;
         plan->cus = cus;
         plan->max_waves_per_cu = maxw;
@@ -182,6 +218,54 @@ sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *s
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
                                           plan->ntiles, waves, plan->wait_limit, b, x, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+        if (!plan->uploaded) return set_err(SPTRSV_ERR_STATE, "plan not uploaded (or rewritten since)");
+        const int32_t n = plan->n;
+        if (n == 0) return SPTRSV_OK;
+        if (!b || !x) return set_err(SPTRSV_ERR_ARG, "null b or x");
+        const size_t nb = (size_t)n * sizeof(double);
+        if (overlaps(b, nb, x, nb)) return set_err(SPTRSV_ERR_ARG, "b and x overlap");
+        if (overlaps(x, nb, plan->dev, plan->layout.total) || overlaps(b, nb, plan->dev, plan->layout.total))
+            return set_err(SPTRSV_ERR_ARG, "b or x overlaps the plan buffer");
+        const int waves = launch_waves(*plan);
+        if (!plan->graph_exec || plan->graph_b != b || plan->graph_x != x || plan->graph_waves != waves) {
+            drop_graph(*plan);
+            hipError_t e;
+            if (!plan->capture_stream) {
+                hipStream_t cs = nullptr;
+                e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+                if (e != hipSuccess) return hip_err(e, "hipStreamCreateWithFlags");
+                plan->capture_stream = cs;
+            }
+            hipStream_t cs = static_cast<hipStream_t>(plan->capture_stream);
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
+            const int le = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
+                                               plan->ntiles, waves, plan->wait_limit, b, x, cs);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cs, &g);
+            if (le != 0) {
+                if (g) hipGraphDestroy(g);
+                return hip_err((hipError_t)le, "kernel launch under capture");
+            }
+            if (e != hipSuccess) return hip_err(e, "hipStreamEndCapture");
+            hipGraphExec_t ge = nullptr;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
+            plan->graph_exec = ge;
+            plan->graph_b = b;
+            plan->graph_x = x;
+            plan->graph_waves = waves;
+        }
+        hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(plan->graph_exec), static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
         return SPTRSV_OK;
     });
 }

@@ -202,8 +202,12 @@ void pack(Plan &p) {
     std::fill(tcol, tcol + nchunks * 64, kPad);
     std::fill(scol, scol + nst * kSegChunks * 64, kPad);
     for (int64_t q = 0; q < nst * 64; ++q) srow[2 * q] = -1;
-    // the device image speaks the caller's indices (reversed for upper input)
-    auto orig = [&](int32_t i) { return p.upper ? n - 1 - i : i; };
+    // the device image speaks the caller's indices (reversed for upper input,
+    // mapped into the right-hand-side blocks for batched input)
+    auto orig = [&](int32_t i) {
+        if (!p.dev_index.empty()) return p.dev_index[(size_t)i];
+        return p.upper ? n - 1 - i : i;
+    };
     for (int32_t s = 0; s < n; ++s) {
         const int32_t i = slot_row[(size_t)s];
         trow[s] = orig(i);

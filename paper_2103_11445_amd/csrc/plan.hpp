@@ -57,6 +57,11 @@ struct Plan {
     // indices
     int32_t n = 0;
     bool upper = false;
+    // device index of each row when it is not the row itself (batched plans:
+    // the rows of a block-diagonal union map into the callers' row-major
+    // right-hand-side blocks); empty otherwise
+    std::vector<int32_t> dev_index;
+    int32_t batch_count = 0;
     std::vector<int32_t> rp, ci;
     std::vector<double> val;
     std::vector<int32_t> level;  // level of each row of L
@@ -90,12 +95,21 @@ struct Plan {
     int max_waves_per_cu = 0;            // co-resident solve workgroups per CU
     int waves_per_cu = 0;                // requested; 0 = chosen from the plan's shape
     uint64_t wait_limit = 200000000ull;  // 2 s at 100 MHz
+
+    // ---- captured solve graph (sptrsv_solve_graph)
+    void *graph_exec = nullptr;          // hipGraphExec_t
+    void *capture_stream = nullptr;      // hipStream_t owned by the plan
+    const void *graph_b = nullptr, *graph_x = nullptr;
+    int graph_waves = 0;
+    ~Plan();
 };
 
 // analyse.cpp
 void validate_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
 void analyse(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
 void analyse_upper(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const double *val);
+void analyse_batch(Plan &p, int32_t count, const int32_t *n, const int32_t *const *rp,
+                   const int32_t *const *ci, const double *const *val, const int32_t *k);
 void level_sets(int32_t n, const int32_t *level, int32_t nlev, std::vector<int32_t> &ptr,
                 std::vector<int32_t> &rows);
 

@@ -261,3 +261,48 @@ def test_upper_errors(sp):
     assert st(2, [0, 2, 3], [0, 1, 0], [2.0, -1.0, 3.0]) == "ERR_CSR"   # below the diagonal
     assert st(2, [0, 1, 2], [1, 1], [2.0, 3.0]) == "ERR_DIAG"           # row 0 has no diagonal
     assert st(2, [0, 2, 3], [0, 1, 1], [0.0, -1.0, 3.0]) == "ERR_DIAG"  # zero diagonal
+
+
+# -------------------------------------------------------------- batches --
+
+def test_batch_plan_is_the_union_plan(sp):
+    """A batched plan equals the oracle plan of the block-diagonal union
+    (k copies of each system), built here independently."""
+    corp = wl.batch_corpus(7, nmin=50, nmax=3000, ks=(1, 2, 3), seed=8)
+    ks = [s.b.shape[1] for s in corp]
+    rows, cols, vals, base = [], [], [], 0
+    rp = [0]
+    for s, k in zip(corp, ks):
+        for c in range(k):
+            for i in range(s.n):
+                seg = slice(s.row_ptr[i], s.row_ptr[i + 1])
+                cols.append(s.col_idx[seg] + base)
+                vals.append(s.val[seg])
+                rp.append(rp[-1] + (s.row_ptr[i + 1] - s.row_ptr[i]))
+            base += s.n
+    rp = np.array(rp, np.int32)
+    ci = np.concatenate(cols).astype(np.int32)
+    v = np.concatenate(vals)
+    pol = {"kind": "threshold", "max_width": 10**9, "max_depth": 3, "max_fill": 10.0}
+    plan = sp.Plan.batch([(s.row_ptr, s.col_idx, s.val) for s in corp], ks)
+    plan.rewrite("threshold", max_width=10**9, max_depth=3, max_fill=10.0)
+    o = oracle.plan(rp, ci, v, pol)
+    assert plan.info()["n"] == rp.size - 1
+    assert np.array_equal(plan.levels(0), o["level"])
+    lp, m = plan.export()
+    for a, b in zip(lp + m, o["lp"] + o["m"]):
+        assert np.array_equal(a, b)
+
+
+def test_batch_errors(sp):
+    s = wl.stencil2d(4, seed=0)
+    with pytest.raises(sp.SptrsvError) as e:
+        sp.Plan.batch([(s.row_ptr, s.col_idx, s.val)], [0])
+    assert e.value.status == "ERR_ARG"
+    bad = s.val.copy()
+    bad[s.row_ptr[3] - 1] = 0.0
+    with pytest.raises(sp.SptrsvError) as e:
+        sp.Plan.batch([(s.row_ptr, s.col_idx, s.val), (s.row_ptr, s.col_idx, bad)])
+    assert e.value.status == "ERR_DIAG" and "system 1" in str(e.value)
+    empty = sp.Plan.batch([])
+    assert empty.info()["n"] == 0

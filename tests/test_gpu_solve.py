@@ -159,3 +159,55 @@ def test_upper_backward_substitution(torch, sp, make, kind, kw):
     x = plan.solve(b)
     assert plan.check() == 0
     assert relerr(x.cpu().numpy(), ref) <= TOL
+
+
+# -------------------------------------------------------------- batches --
+
+def _batch_rhs(corp):
+    return np.concatenate([s.b.reshape(-1) for s in corp])
+
+
+def _batch_refs(corp):
+    return [oracle.solve(s.row_ptr, s.col_idx, s.val, s.b) for s in corp]
+
+
+def _check_batch(corp, xall):
+    off = 0
+    for s, ref in zip(corp, _batch_refs(corp)):
+        k = s.b.shape[1]
+        got = xall[off:off + s.n * k].reshape(s.n, k)
+        off += s.n * k
+        assert relerr(got, ref.reshape(s.n, k)) <= TOL, s.name
+
+
+@pytest.mark.parametrize("kind,kw", POLICIES)
+def test_batch_parity(torch, sp, kind, kw):
+    """Many uneven systems with 1..32 right-hand sides, one launch."""
+    corp = wl.batch_corpus(16, nmin=500, nmax=20000, seed=41)
+    plan = sp.Plan.batch([(s.row_ptr, s.col_idx, s.val) for s in corp], [s.b.shape[1] for s in corp])
+    plan.rewrite(kind, **kw).upload()
+    b = torch.from_numpy(_batch_rhs(corp)).cuda()
+    x = plan.solve(b)
+    assert plan.check() == 0
+    _check_batch(corp, x.cpu().numpy())
+
+
+def test_graph_replays_match_eager(torch, sp):
+    """The captured solve, replayed several times with eager work and
+    synchronisations in between, gives the eager result every time."""
+    corp = wl.batch_corpus(10, nmin=500, nmax=10000, seed=42)
+    plan = sp.Plan.batch([(s.row_ptr, s.col_idx, s.val) for s in corp], [s.b.shape[1] for s in corp])
+    plan.rewrite("threshold", max_width=10**9, max_depth=4, max_fill=10.0).upload()
+    b = torch.from_numpy(_batch_rhs(corp)).cuda()
+    eager = plan.solve(b).cpu().numpy()
+    x = torch.empty_like(b)
+    for rep in range(5):
+        x.fill_(float("nan"))
+        y = torch.randn(1000, device="cuda").sum()  # unrelated eager work
+        plan.solve_graph(b, x)
+        torch.cuda.synchronize()
+        assert float(y) == float(y)
+        got = x.cpu().numpy()
+        assert np.array_equal(got.view(np.int64), eager.view(np.int64)), rep
+    assert plan.check() == 0
+    _check_batch(corp, eager)

@@ -38,7 +38,7 @@ import numpy as np
 
 __all__ = [
     "System", "assemble", "stencil2d", "stencil3d", "banded", "powerlaw",
-    "random_lower", "bidiagonal", "diagonal", "from_pairs", "transpose", "config",
+    "random_lower", "bidiagonal", "diagonal", "from_pairs", "transpose", "batch_corpus", "config",
     "CONFIGS", "rhs",
 ]
 
@@ -261,6 +261,33 @@ def transpose(s: System, name: str | None = None) -> System:
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(np.bincount(t_rows, minlength=n), out=row_ptr[1:])
     return System(name or s.name + "_T", row_ptr.astype(np.int32), t_cols, s.val[order], s.b)
+
+
+def batch_corpus(count: int = 64, nmin: int = 1_000, nmax: int = 200_000, ks=(1, 4, 8, 32),
+                 seed: int = 4) -> list:
+    """Many systems of uneven size: n log-uniform in [nmin, nmax], family
+    uniform over {2D stencil, 3D stencil, banded, power-law}, and k drawn
+    from ``ks`` right-hand sides (row-major n x k).  System j is drawn from
+    seed 40000 + j (the family, size and k of all systems from ``seed``)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
+        fam = int(rng.integers(0, 4))
+        k = int(rng.choice(ks))
+        sd = 40000 + j
+        if fam == 0:
+            s = stencil2d(max(2, int(round(n ** 0.5))), seed=sd, k=k)
+        elif fam == 1:
+            s = stencil3d(max(2, int(round(n ** (1 / 3)))), seed=sd, k=k)
+        elif fam == 2:
+            s = banded(n, min(200, max(1, n // 2)), 8, 24, seed=sd, k=k)
+        else:
+            s = powerlaw(n, max(1, n // 200), seed=sd, k=k)
+        if k == 1:
+            s.b = s.b.reshape(-1, 1)
+        out.append(s)
+    return out
 
 
 # ------------------------------------------------------ named workloads --
