@@ -162,15 +162,49 @@ sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void 
  * level order), so the level structure bounds the critical path.  Numerical problems are not
  * reported (zero diagonals were rejected by analyse); a dependency wait
  * that exceeds the wait limit is reported by sptrsv_check.  Errors: ARG,
- * STATE (not uploaded or stale), HIP. */
+ * STATE (not uploaded, stale, or stored in FP32), HIP. */
 sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *stream);
 
-/* As sptrsv_solve, through a HIP graph: the fill and solve launches are
+/* As sptrsv_solve (FP64 plans), through a HIP graph: the fill and solve launches are
  * captured once (on a stream the plan owns) for these b and x and replayed
  * on `stream` by later calls with the same pointers (a different b, x, launch
  * shape, rewrite or upload captures again).  For callers that replay one
  * solve many times.  Errors: as sptrsv_solve, HIP (capture refused). */
 sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, void *stream);
+
+/* Value type of the device image: 64 (FP64, the default) or 32.  A plan
+ * stored in FP32 keeps every value of L' and M and every diagonal rounded to
+ * nearest FP32 and solves in FP32 arithmetic (sptrsv_solve_fp32), with x in
+ * FP32; it also carries the caller's matrices in FP64 for the residual of
+ * sptrsv_solve_refined.  Repacks the host image (the upload becomes stale);
+ * the schedule, the rewrite and the introspection calls are unchanged.  The
+ * precision survives later rewrites.  Errors: ARG (bits not 32 or 64),
+ * OVERFLOW, OOM. */
+sptrsv_status sptrsv_set_precision(sptrsv_plan plan, int32_t bits);
+
+/* As sptrsv_solve for a plan stored in FP32: b and x are device arrays of n
+ * floats.  Errors: as sptrsv_solve; STATE for a plan stored in FP64. */
+sptrsv_status sptrsv_solve_fp32(sptrsv_plan plan, const float *b, float *x, void *stream);
+
+/* Mixed-precision iterative refinement for a plan stored in FP32 (an
+ * extension; the paper's solve is a single pass): b and x are device arrays
+ * of n doubles.  With x = 0 and r = b, each step solves L d = r (r rounded to
+ * FP32) with the FP32 schedule, updates x += d in FP64 and recomputes
+ * r = b - L x in FP64 with the caller's FP64 matrix.  After step t >= 1 the
+ * largest correction |d_i| / max(|x_i|, 1e-3 max_j |x_j|) is compared with
+ * tol on the device; once it is <= tol the remaining steps do nothing.
+ * At most `iterations` (1..16) steps; everything is enqueued on stream
+ * without waiting.  sptrsv_refine_stats reports the steps taken.  Errors: as
+ * sptrsv_solve_fp32; ARG (iterations out of range, tol < 0 or NaN). */
+sptrsv_status sptrsv_solve_refined(sptrsv_plan plan, const double *b, double *x, int32_t iterations,
+                                   double tol, void *stream);
+
+/* Waits for stream, then reports the last refinement: *iterations = steps
+ * applied, *correction = the relative correction of the last step applied
+ * (+inf after a single step).  Errors: ARG, STATE (not uploaded, or FP64
+ * plan), HIP. */
+sptrsv_status sptrsv_refine_stats(sptrsv_plan plan, void *stream, int32_t *iterations,
+                                  double *correction);
 
 /* Waits for stream, then reads and clears the plan's device status word:
  * *device_status = 0 if every solve since the last check completed normally,
@@ -191,9 +225,10 @@ sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks);
 
 /* Plan statistics (Sec. V reports levels and FLOPs before and after).
  * flops: 2 per stored off-diagonal x-term or b-term plus 1 per row.
- * bytes: compulsory traffic of one solve, 12 per stored entry (int32 column +
- * FP64 value, diagonals included) + 24 per row (row offset, row id, b_i,
- * x_i); gathers of x and b are counted as cache hits. */
+ * bytes: compulsory traffic of one solve in the plan's value type (v = 8
+ * bytes for FP64, 4 for FP32): 4 + v per stored entry (int32 column + value,
+ * diagonals included) + 8 + 2v per row (row offset, row id, b_i, x_i);
+ * gathers of x and b are counted as cache hits. */
 typedef struct {
     int32_t n;
     int32_t levels;      /* levels of L */
@@ -208,6 +243,7 @@ typedef struct {
     int64_t bytes_rw;    /* of the rewritten solve */
     int64_t device_bytes;/* size of the device image + workspace */
     int64_t tiles;       /* 64-lane work tiles in the device schedule */
+    int32_t precision;   /* 64 or 32: value type of the device image */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

@@ -50,7 +50,8 @@ class _Info(ctypes.Structure):
                 ("levels_rw", ctypes.c_int32), ("nnz", ctypes.c_int64), ("nnz_rw", ctypes.c_int64),
                 ("nnz_m", ctypes.c_int64), ("flops", ctypes.c_int64), ("flops_rw", ctypes.c_int64),
                 ("bytes", ctypes.c_int64), ("bytes_rw", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("precision", ctypes.c_int32)]
 
 
 _lib = None
@@ -80,6 +81,10 @@ def load():
         "sptrsv_device_bytes": (S, [P, P]),
         "sptrsv_upload": (S, [P, P, ctypes.c_size_t, P]),
         "sptrsv_solve": (S, [P, P, P, P]),
+        "sptrsv_solve_fp32": (S, [P, P, P, P]),
+        "sptrsv_solve_refined": (S, [P, P, P, I32, ctypes.c_double, P]),
+        "sptrsv_refine_stats": (S, [P, P, P, P]),
+        "sptrsv_set_precision": (S, [P, I32]),
         "sptrsv_check": (S, [P, P, P]),
         "sptrsv_set_wait_limit": (S, [P, U64]),
         "sptrsv_set_launch": (S, [P, I32]),
@@ -218,6 +223,11 @@ class Plan:
     def set_wait_limit(self, ticks: int):
         _check(load().sptrsv_set_wait_limit(self._h, int(ticks)))
 
+    def set_precision(self, bits: int) -> "Plan":
+        """Value type of the device image: 64 or 32 (repacks; upload again)."""
+        _check(load().sptrsv_set_precision(self._h, int(bits)))
+        return self
+
     # -------------------------------------------------------- device side --
     def upload(self, device=None, stream=None) -> "Plan":
         """Allocate the device buffer with torch and copy the plan into it."""
@@ -245,6 +255,31 @@ class Plan:
             x = torch.empty_like(b)
         _check(load().sptrsv_solve_graph(self._h, _ptr(b), _ptr(x), _stream(stream)))
         return x
+
+    def solve_fp32(self, b, x=None, stream=None):
+        """Enqueue the FP32 solve of a plan stored in FP32 (float32 tensors)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().sptrsv_solve_fp32(self._h, _ptr(b), _ptr(x), _stream(stream)))
+        return x
+
+    def solve_refined(self, b, x=None, iterations: int = 10, tol: float = 1e-13, stream=None):
+        """Enqueue FP32 solves refined by FP64 residuals and updates (plan
+        stored in FP32; float64 tensors)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().sptrsv_solve_refined(self._h, _ptr(b), _ptr(x), int(iterations), float(tol),
+                                           _stream(stream)))
+        return x
+
+    def refine_stats(self, stream=None):
+        """(steps applied, relative correction of the last step)."""
+        it = ctypes.c_int32()
+        corr = ctypes.c_double()
+        _check(load().sptrsv_refine_stats(self._h, _stream(stream), ctypes.byref(it), ctypes.byref(corr)))
+        return it.value, corr.value
 
     def check(self, stream=None) -> int:
         st = ctypes.c_int32()

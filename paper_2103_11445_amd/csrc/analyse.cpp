@@ -64,6 +64,9 @@ void analyse(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, const dou
     }
     p.nlev = maxlev + 1;
     level_sets(n, p.level.data(), p.nlev, p.level_ptr, p.level_rows);
+    p.sys_n.assign(1, n);
+    p.sys_k.assign(1, 1);
+    p.sys_base.assign(1, 0);
 }
 
 // Upper-triangular U (diagonal first in each row): validate, then hold it with
@@ -153,6 +156,13 @@ void analyse_batch(Plan &p, int32_t count, const int32_t *n, const int32_t *cons
     analyse(p, (int32_t)rows, urp.data(), uci.data(), uval.data());
     p.dev_index = std::move(index);
     p.batch_count = count;
+    p.sys_n.assign(n, n + count);
+    p.sys_k.assign(k, k + count);
+    p.sys_base.resize((size_t)count);
+    for (int32_t j = 0, b = 0; j < count; ++j) {
+        p.sys_base[(size_t)j] = b;
+        b += n[j] * k[j];
+    }
 }
 
 }  // namespace sptrsv

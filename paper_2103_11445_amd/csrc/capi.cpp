@@ -203,36 +203,111 @@ sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void 
     });
 }
 
+}  // extern "C"
+
+namespace {
+// Common checks of the solve entry points; 1 when there is nothing to do
+// (n == 0), 0 when the solve may be enqueued.  Throws on a bad call.
+int solve_args_ok(const sptrsv::Plan *plan, const void *b, const void *x, int precision, size_t elem) {
+    if (!plan) throw sptrsv::Error{SPTRSV_ERR_ARG, "plan is NULL"};
+    if (!plan->uploaded) throw sptrsv::Error{SPTRSV_ERR_STATE, "plan not uploaded (or rewritten since)"};
+    if (plan->precision != precision)
+        throw sptrsv::Error{SPTRSV_ERR_STATE, precision == 64
+                                                  ? "plan is stored in FP32: use sptrsv_solve_fp32 or sptrsv_solve_refined"
+                                                  : "plan is stored in FP64: set FP32 with sptrsv_set_precision"};
+    const int32_t n = plan->n;
+    if (n == 0) return 1;
+    if (!b || !x) throw sptrsv::Error{SPTRSV_ERR_ARG, "null b or x"};
+    const size_t nb = (size_t)n * elem;
+    if (overlaps(b, nb, x, nb)) throw sptrsv::Error{SPTRSV_ERR_ARG, "b and x overlap"};
+    if (overlaps(x, nb, plan->dev, plan->layout.total) || overlaps(b, nb, plan->dev, plan->layout.total))
+        throw sptrsv::Error{SPTRSV_ERR_ARG, "b or x overlaps the plan buffer"};
+    return 0;
+}
+}  // namespace
+
+extern "C" {
+
 sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *stream) {
     return guarded([&]() -> sptrsv_status {
-        if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
-        if (!plan->uploaded) return set_err(SPTRSV_ERR_STATE, "plan not uploaded (or rewritten since)");
-        const int32_t n = plan->n;
-        if (n == 0) return SPTRSV_OK;
-        if (!b || !x) return set_err(SPTRSV_ERR_ARG, "null b or x");
-        const size_t nb = (size_t)n * sizeof(double);
-        if (overlaps(b, nb, x, nb)) return set_err(SPTRSV_ERR_ARG, "b and x overlap");
-        if (overlaps(x, nb, plan->dev, plan->layout.total) || overlaps(b, nb, plan->dev, plan->layout.total))
-            return set_err(SPTRSV_ERR_ARG, "b or x overlaps the plan buffer");
+        if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
         const int waves = launch_waves(*plan);
-        const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
+        const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
                                           plan->ntiles, waves, plan->wait_limit, b, x, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
 }
 
-sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, void *stream) {
+sptrsv_status sptrsv_solve_fp32(sptrsv_plan plan, const float *b, float *x, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (solve_args_ok(plan, b, x, 32, sizeof(float))) return SPTRSV_OK;
+        const int waves = launch_waves(*plan);
+        const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
+                                          plan->ntiles, waves, plan->wait_limit, b, x, stream);
+        if (e != 0) return hip_err((hipError_t)e, "kernel launch");
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_solve_refined(sptrsv_plan plan, const double *b, double *x, int32_t iterations,
+                                   double tol, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (iterations < 1 || iterations > sptrsv::kMaxRefine)
+            return set_err(SPTRSV_ERR_ARG, "iterations must be in [1, 16]");
+        if (!(tol >= 0.0)) return set_err(SPTRSV_ERR_ARG, "tol must be >= 0");
+        if (solve_args_ok(plan, b, x, 32, sizeof(double))) return SPTRSV_OK;
+        const int waves = launch_waves(*plan);
+        const int e = sptrsv_launch_refined(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
+                                            plan->ntiles, waves, plan->wait_limit, b, x, iterations, tol, stream);
+        if (e != 0) return hip_err((hipError_t)e, "kernel launch");
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_refine_stats(sptrsv_plan plan, void *stream, int32_t *iterations, double *correction) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan || !iterations || !correction) return set_err(SPTRSV_ERR_ARG, "null argument");
+        if (!plan->uploaded) return set_err(SPTRSV_ERR_STATE, "plan not uploaded");
+        if (plan->precision != 32) return set_err(SPTRSV_ERR_STATE, "plan is stored in FP64");
+        hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+        sptrsv::Workspace w;
+        e = hipMemcpy(&w, static_cast<unsigned char *>(plan->dev) + plan->layout.workspace, sizeof(w),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_err(e, "hipMemcpy");
+        *iterations = (int32_t)w.iters;
+        double r = 0.0;
+        if (w.iters > 0) std::memcpy(&r, &w.ratio[w.iters - 1], sizeof(r));
+        *correction = w.iters > 0 ? r : 0.0;
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_set_precision(sptrsv_plan plan, int32_t bits) {
     return guarded([&]() -> sptrsv_status {
         if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
-        if (!plan->uploaded) return set_err(SPTRSV_ERR_STATE, "plan not uploaded (or rewritten since)");
+        if (bits != 32 && bits != 64) return set_err(SPTRSV_ERR_ARG, "bits must be 32 or 64");
+        if (bits == plan->precision) return SPTRSV_OK;
+        const int old = plan->precision;
+        plan->precision = bits;
+        plan->uploaded = false;
+        drop_graph(*plan);
+        try {
+            sptrsv::pack(*plan);
+        } catch (...) {
+            plan->precision = old;
+            sptrsv::pack(*plan);
+            throw;
+        }
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
         const int32_t n = plan->n;
-        if (n == 0) return SPTRSV_OK;
-        if (!b || !x) return set_err(SPTRSV_ERR_ARG, "null b or x");
-        const size_t nb = (size_t)n * sizeof(double);
-        if (overlaps(b, nb, x, nb)) return set_err(SPTRSV_ERR_ARG, "b and x overlap");
-        if (overlaps(x, nb, plan->dev, plan->layout.total) || overlaps(b, nb, plan->dev, plan->layout.total))
-            return set_err(SPTRSV_ERR_ARG, "b or x overlaps the plan buffer");
         const int waves = launch_waves(*plan);
         if (!plan->graph_exec || plan->graph_b != b || plan->graph_x != x || plan->graph_waves != waves) {
             drop_graph(*plan);
@@ -315,10 +390,12 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->nnz_m = p.m_ptr.empty() ? 0 : p.m_ptr.back();
     o->flops = 2 * (o->nnz - p.n) + p.n;
     o->flops_rw = 2 * (o->nnz_rw - p.n + o->nnz_m) + p.n;
-    o->bytes = 12 * o->nnz + 24 * (int64_t)p.n;
-    o->bytes_rw = 12 * (o->nnz_rw + o->nnz_m) + 24 * (int64_t)p.n;
+    const int64_t vb = p.precision / 8;
+    o->bytes = (4 + vb) * o->nnz + (8 + 2 * vb) * (int64_t)p.n;
+    o->bytes_rw = (4 + vb) * (o->nnz_rw + o->nnz_m) + (8 + 2 * vb) * (int64_t)p.n;
     o->device_bytes = (int64_t)p.layout.total;
     o->tiles = p.ntiles;
+    o->precision = p.precision;
     return SPTRSV_OK;
 }
 

@@ -164,7 +164,11 @@ void pack(Plan &p) {
 
     // ---- layout
     const int64_t nst = (int64_t)stiles.size();
+    const bool f32 = p.precision == 32;
+    const size_t vb = f32 ? 4 : 8;
     Layout &Ly = p.layout;
+    Ly = Layout{};
+    Ly.value_bytes = (int)vb;
     size_t off = 0;
     Ly.workspace = off;
     off = align256(off + sizeof(Workspace));
@@ -173,32 +177,57 @@ void pack(Plan &p) {
     Ly.rows = off;
     off = align256(off + (size_t)n * 4);
     Ly.diag = off;
-    off = align256(off + (size_t)n * 8);
+    off = align256(off + (size_t)n * vb);
     Ly.tcol = off;
     off = align256(off + (size_t)nchunks * 64 * 4);
     Ly.tval = off;
-    off = align256(off + (size_t)nchunks * 64 * 8);
+    off = align256(off + (size_t)nchunks * 64 * vb);
     Ly.scol = off;
     off = align256(off + (size_t)nst * kSegChunks * 64 * 4);
     Ly.sval = off;
-    off = align256(off + (size_t)nst * kSegChunks * 64 * 8);
+    off = align256(off + (size_t)nst * kSegChunks * 64 * vb);
     Ly.srow = off;
     off = align256(off + (size_t)nst * 64 * 8);
     Ly.sdiag = off;
-    off = align256(off + (size_t)nst * 64 * 8);
+    off = align256(off + (size_t)nst * 64 * vb);
+    if (f32) {
+        Ly.nsys = (int32_t)p.sys_n.size();
+        for (size_t j = 0; j < p.sys_n.size(); ++j) {
+            const int32_t nj = p.sys_n[j];
+            const int64_t r0 = p.upper ? 0 : p.sys_base[j];
+            Ly.res_rows += nj;
+            Ly.res_nnz += nj ? (int64_t)p.rp[(size_t)(r0 + nj)] - p.rp[(size_t)r0] : 0;
+        }
+        if (Ly.res_nnz > INT32_MAX) throw Error{SPTRSV_ERR_OVERFLOW, "residual matrix beyond int32 indexing"};
+        Ly.sys = off;
+        off = align256(off + (size_t)Ly.nsys * 16);
+        Ly.res_rp = off;
+        off = align256(off + (size_t)(Ly.res_rows + 1) * 4);
+        Ly.res_col = off;
+        off = align256(off + (size_t)Ly.res_nnz * 4);
+        Ly.res_val = off;
+        off = align256(off + (size_t)Ly.res_nnz * 8);
+        Ly.r32 = off;
+        off = align256(off + (size_t)n * 4);
+        Ly.d32 = off;
+        off = align256(off + (size_t)n * 4);
+    }
     Ly.total = off;
 
     p.image.assign(Ly.total, 0);
     unsigned char *img = p.image.data();
     int32_t *trow = reinterpret_cast<int32_t *>(img + Ly.rows);
-    double *tdiag = reinterpret_cast<double *>(img + Ly.diag);
     int32_t *tcol = reinterpret_cast<int32_t *>(img + Ly.tcol);
-    double *tval = reinterpret_cast<double *>(img + Ly.tval);
     int32_t *desc = reinterpret_cast<int32_t *>(img + Ly.tiles);
     int32_t *scol = reinterpret_cast<int32_t *>(img + Ly.scol);
-    double *sval = reinterpret_cast<double *>(img + Ly.sval);
     int32_t *srow = reinterpret_cast<int32_t *>(img + Ly.srow);  // {row, meta} per lane
-    double *sdiag = reinterpret_cast<double *>(img + Ly.sdiag);
+    // value sections: FP64, or rounded to nearest FP32
+    auto putv = [&](size_t section, int64_t idx, double v) {
+        if (f32)
+            reinterpret_cast<float *>(img + section)[idx] = (float)v;
+        else
+            reinterpret_cast<double *>(img + section)[idx] = v;
+    };
     std::fill(tcol, tcol + nchunks * 64, kPad);
     std::fill(scol, scol + nst * kSegChunks * 64, kPad);
     for (int64_t q = 0; q < nst * 64; ++q) srow[2 * q] = -1;
@@ -211,7 +240,7 @@ void pack(Plan &p) {
     for (int32_t s = 0; s < n; ++s) {
         const int32_t i = slot_row[(size_t)s];
         trow[s] = orig(i);
-        tdiag[s] = p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1];
+        putv(Ly.diag, s, p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1]);
     }
 
     // terms of row i for a tile with 2^lg lanes per row, written through put(col, val)
@@ -249,13 +278,13 @@ void pack(Plan &p) {
                     const int64_t lead = st * 64 + r * g;
                     srow[2 * lead] = orig(i);
                     srow[2 * lead + 1] = T.lg | (((s - seg_first[(size_t)sid]) & (kRing - 1)) << 8);
-                    sdiag[lead] = tdiag[s];
+                    putv(Ly.sdiag, lead, p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1]);
                     int64_t t_ = 0;
                     row_terms(i, sid, T.row_off, [&](int32_t col, double v) {
                         const int64_t ln = st * 64 + r * g + (t_ & (g - 1));
                         const int64_t idx = ln * kSegChunks + (t_ >> T.lg);
                         scol[idx] = col;
-                        sval[idx] = v;
+                        putv(Ly.sval, idx, v);
                         ++t_;
                     });
                 }
@@ -274,9 +303,37 @@ void pack(Plan &p) {
             row_terms(i, -1, 0, [&](int32_t col, double v) {
                 const int64_t idx = (T.chunk_off + (t_ >> T.lg)) * 64 + r * g + (t_ & (g - 1));
                 tcol[idx] = col;
-                tval[idx] = v;
+                putv(Ly.tval, idx, v);
                 ++t_;
             });
+        }
+    }
+    if (f32) {
+        // the caller's matrices in FP64 (device indices) for the residual
+        int32_t *sys = reinterpret_cast<int32_t *>(img + Ly.sys);
+        int32_t *rrp = reinterpret_cast<int32_t *>(img + Ly.res_rp);
+        int32_t *rcol = reinterpret_cast<int32_t *>(img + Ly.res_col);
+        double *rval = reinterpret_cast<double *>(img + Ly.res_val);
+        int64_t row = 0, q = 0;
+        rrp[0] = 0;
+        for (size_t j = 0; j < p.sys_n.size(); ++j) {
+            const int32_t nj = p.sys_n[j], kj = p.sys_k[j];
+            const int64_t base = p.sys_base[j];
+            sys[4 * j + 0] = (int32_t)base;
+            sys[4 * j + 1] = nj;
+            sys[4 * j + 2] = kj;
+            sys[4 * j + 3] = (int32_t)row;
+            for (int32_t i = 0; i < nj; ++i) {
+                // plan row holding the caller's row i (copy 0 of a batched system)
+                const int64_t r = p.upper ? (int64_t)n - 1 - i : base + i;
+                for (int32_t t = p.rp[(size_t)r]; t < p.rp[(size_t)r + 1]; ++t) {
+                    const int64_t l = p.upper ? (int64_t)n - 1 - p.ci[(size_t)t] : p.ci[(size_t)t] - base;
+                    rcol[q] = (int32_t)(base + l * kj);
+                    rval[q] = p.val[(size_t)t];
+                    ++q;
+                }
+                rrp[++row] = (int32_t)q;
+            }
         }
     }
     p.ntiles = (int64_t)items.size();

@@ -24,9 +24,13 @@ constexpr int kNarrowTiles = 2;   // a level of at most this many segment tiles 
 constexpr int kMinSegLevels = 16; // shortest run of narrow levels executed as a segment
 constexpr int kSegDepth = 4;      // segment software-pipeline depth; segments hold a multiple of it
 
+constexpr int kMaxRefine = 16;    // refinement iterations per call (slots in the workspace)
+
 // Device image layout: byte offsets of each section inside the caller's
-// buffer.  Sections are 256-byte aligned.
+// buffer.  Sections are 256-byte aligned.  Values (diag, tval, sval, sdiag)
+// are FP64, or FP32 in a plan stored in FP32 (value_bytes 4).
 struct Layout {
+    int value_bytes = 8;
     size_t workspace = 0;  // Workspace block
     size_t tiles = 0;      // int4[nitems]: wide tile {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
                            //   or segment {first segment tile, count, 0, 1<<31}
@@ -39,16 +43,33 @@ struct Layout {
     size_t srow = 0;       // int32[nseg_tiles][64][2]: row finished by the lane (-1 if none),
                            //   log2 lanes per row | ring index << 8
     size_t sdiag = 0;      // double[nseg_tiles][64] its diagonal
+    // FP32 plans only: what iterative refinement needs next to the FP32
+    // schedule -- the caller's matrices in FP64 for the residual, and two
+    // FP32 vectors (residual, correction) indexed like b and x
+    size_t sys = 0;        // int4[nsys] {device base, rows, right-hand sides, first residual row}
+    size_t res_rp = 0;     // int32[res_rows + 1]
+    size_t res_col = 0;    // int32[res_nnz] device index of column l for right-hand side 0: base + l*k
+    size_t res_val = 0;    // double[res_nnz]
+    size_t r32 = 0;        // float[n]
+    size_t d32 = 0;        // float[n]
+    int32_t nsys = 0;
+    int64_t res_rows = 0, res_nnz = 0;
     size_t total = 0;
 };
 
 // Per-solve bookkeeping shared by the kernels (lives at layout.workspace).
 struct Workspace {
     unsigned int status;  // 0 ok, else SPTRSV_ERR_TIMEOUT; cleared by sptrsv_check
+    unsigned int done;    // refinement: converged, later steps skip their work
+    unsigned int iters;   // refinement: corrections applied by the last call
     unsigned int pad0;
-    unsigned long long pad[7];
+    // refinement, per iteration t: max |x| after the update (FP64 bits), and
+    // the largest correction relative to max(|x_i|, 1e-3 max|x|)
+    unsigned long long xmax[kMaxRefine];
+    unsigned long long ratio[kMaxRefine];
+    unsigned long long pad[30];
 };
-static_assert(sizeof(Workspace) == 64, "workspace block is one cache line");
+static_assert(sizeof(Workspace) == 512, "workspace block is 512 bytes");
 
 struct Plan {
     // ---- analysed matrix (Sec. II / IV); for an upper-triangular input the
@@ -62,6 +83,13 @@ struct Plan {
     // right-hand-side blocks); empty otherwise
     std::vector<int32_t> dev_index;
     int32_t batch_count = 0;
+    // the caller's systems as the plan holds them: rows, right-hand sides
+    // and device base of each (one entry for an unbatched plan)
+    std::vector<int32_t> sys_n, sys_k;
+    std::vector<int64_t> sys_base;
+    // value type of the device image: 64 (FP64) or 32 (FP32 storage and
+    // arithmetic, refined to FP64 by sptrsv_solve_refined)
+    int precision = 64;
     std::vector<int32_t> rp, ci;
     std::vector<double> val;
     std::vector<int32_t> level;  // level of each row of L
@@ -122,8 +150,15 @@ void pack(Plan &p);
 
 }  // namespace sptrsv
 
-// solve.hip -- kernel launchers (return a hipError_t as int)
+// solve.hip -- kernel launchers (return a hipError_t as int).  b and x are
+// double or float as lay->value_bytes says.
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay,
                                    int32_t n, int64_t nitems, int waves, uint64_t wait_limit,
-                                   const double *b, double *x, void *stream);
+                                   const void *b, void *x, void *stream);
+// FP32 plans: `iterations` refinement steps on x (FP64), all on stream; the
+// steps after convergence (correction <= tol) skip their work on the device.
+extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay,
+                                     int32_t n, int64_t nitems, int waves, uint64_t wait_limit,
+                                     const double *b, double *x, int iterations, double tol,
+                                     void *stream);
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu);

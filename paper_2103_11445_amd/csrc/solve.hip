@@ -25,6 +25,10 @@
 //     ahead, b / external-x gathers kDepth/2 tiles ahead, so the critical
 //     path waits only on LDS and on loads issued several tiles before.
 //   * b-terms (the rewritten right-hand side) never wait.
+//   * The same kernels run in FP64 or, for plans stored in FP32, in FP32
+//     (values, arithmetic and x; the readiness pattern is then an FP32
+//     signalling NaN); iterative refinement adds an FP64 residual and an
+//     FP64 update around the FP32 solve.
 //   * A wait is bounded by the GPU real-time clock; on expiry the worker
 //     marks the plan's status word, which makes every other wait give up,
 //     and the grid drains with NaNs.
@@ -45,27 +49,45 @@
 
 namespace {
 
-constexpr unsigned long long kNotReady = 0x7FF0DEADBEEF0001ull;  // signalling NaN
-constexpr long long kQuietNaN = 0x7FF8000000000000ll;
 constexpr int32_t kPad = INT32_MIN;
 constexpr int kRegChunks = 4;  // chunks of a wide tile held in registers; more are streamed
 constexpr int kDepth = sptrsv::kSegDepth;  // segment pipeline depth (tiles)
 constexpr int kSegChunks = sptrsv::kSegChunks;
 constexpr int kRing = sptrsv::kRing;
 
+// Per value type: the bit pattern of "not yet published" (a signalling NaN
+// no arithmetic can produce) and of the NaN a failed wait yields.
+template <typename T> struct Val;
+template <> struct Val<double> {
+    using Bits = unsigned long long;
+    static constexpr Bits kNotReady = 0x7FF0DEADBEEF0001ull;
+    static constexpr Bits kQuietNaN = 0x7FF8000000000000ull;
+    __device__ static double of(Bits b) { return __longlong_as_double((long long)b); }
+    __device__ static Bits bits(double v) { return (Bits)__double_as_longlong(v); }
+};
+template <> struct Val<float> {
+    using Bits = unsigned int;
+    static constexpr Bits kNotReady = 0x7FA0DEADu;
+    static constexpr Bits kQuietNaN = 0x7FC00000u;
+    __device__ static float of(Bits b) { return __uint_as_float(b); }
+    __device__ static Bits bits(float v) { return __float_as_uint(v); }
+};
+
+template <typename T>
 struct SolveArgs {
     const int4 *items;
     const int32_t *rows;
-    const double *diag;
+    const T *diag;
     const int32_t *tcol;
-    const double *tval;
+    const T *tval;
     const int32_t *scol;
-    const double *sval;
+    const T *sval;
     const int2 *srow;
-    const double *sdiag;
+    const T *sdiag;
     sptrsv::Workspace *ws;
-    const double *b;
-    double *x;
+    const unsigned *skip;  // refinement: the grid returns at once if *skip (NULL: never)
+    const T *b;
+    T *x;
     long long nitems;
     long long waves;
     unsigned long long wait_limit;
@@ -74,14 +96,17 @@ struct SolveArgs {
 
 __device__ inline bool is_segment(const int4 d) { return d.w < 0; }
 
-__global__ void fill_not_ready(unsigned long long *__restrict__ x, int32_t n) {
+template <typename T>
+__global__ void fill_not_ready(typename Val<T>::Bits *__restrict__ x, int32_t n) {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        x[i] = kNotReady;
+        x[i] = Val<T>::kNotReady;
 }
 
-__device__ inline unsigned long long load_agent(const double *p) {
-    return __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<double *>(p)),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ inline typename Val<T>::Bits load_agent(const T *p) {
+    using B = typename Val<T>::Bits;
+    return __hip_atomic_load(reinterpret_cast<B *>(const_cast<T *>(p)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // First attempt at a gather: an ordinary (cached) load.  Stream order makes
@@ -90,42 +115,46 @@ __device__ inline unsigned long long load_agent(const double *p) {
 // pattern or the final value: a stale pattern only sends the lane to the
 // device-scope poll, never yields a wrong value.  It lets repeated gathers
 // of a published value hit in L2 instead of going to memory each time.
-__device__ inline unsigned long long load_cached(const double *p) {
-    return *reinterpret_cast<const unsigned long long *>(p);
+template <typename T>
+__device__ inline typename Val<T>::Bits load_cached(const T *p) {
+    return *reinterpret_cast<const typename Val<T>::Bits *>(p);
 }
 
 // Bits of x[k] once it is published (a quiet NaN if the wait gave up).
 // Only reached behind a wave-uniform branch (see resolve_pending), so the
 // call and the waits it implies stay off the path where nothing is pending.
-__device__ __noinline__ unsigned long long wait_slow(const double *x, int32_t k, sptrsv::Workspace *ws,
-                                                     unsigned long long limit) {
+template <typename T>
+__device__ __noinline__ typename Val<T>::Bits wait_slow(const T *x, int32_t k, sptrsv::Workspace *ws,
+                                                        unsigned long long limit) {
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     for (unsigned it = 1;; ++it) {
         __builtin_amdgcn_s_sleep(1);
-        const unsigned long long v = load_agent(x + k);
-        if (v != kNotReady) return v;
+        const typename Val<T>::Bits v = load_agent(x + k);
+        if (v != Val<T>::kNotReady) return v;
         if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
             __hip_atomic_fetch_or(&ws->status, (unsigned)SPTRSV_ERR_TIMEOUT, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
-            return (unsigned long long)kQuietNaN;
+            return Val<T>::kQuietNaN;
         }
         if ((it & 15u) == 0 &&
             __hip_atomic_load(&ws->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
-            return (unsigned long long)kQuietNaN;
+            return Val<T>::kQuietNaN;
     }
 }
 
 // Address a term gathers from: x_k for x-terms (0 <= k < n), b_j for b-terms
 // (k = ~j), the dummy b_0 otherwise.
-__device__ inline const double *gather_addr(const SolveArgs &a, int32_t k) {
-    const double *p = a.b;
+template <typename T>
+__device__ inline const T *gather_addr(const SolveArgs<T> &a, int32_t k) {
+    const T *p = a.b;
     if (k >= 0 && k < a.n) p = a.x + k;
     if (k < 0 && k != kPad) p = a.b + ~k;
     return p;
 }
 
-__device__ inline bool pending(const SolveArgs &a, int32_t k, unsigned long long v) {
-    return k >= 0 && k < a.n && v == kNotReady;
+template <typename T>
+__device__ inline bool pending(const SolveArgs<T> &a, int32_t k, typename Val<T>::Bits v) {
+    return k >= 0 && k < a.n && v == Val<T>::kNotReady;
 }
 
 // Waits for every gathered x-term that was not yet published.  The test is a
@@ -138,8 +167,8 @@ __device__ inline bool pending(const SolveArgs &a, int32_t k, unsigned long long
 //     to one lane per waiting wave (waves run ahead of the frontier).
 //   otherwise (segments, which rarely wait and then on a single row just
 //     produced by another wave): every pending lane polls its own term.
-template <int kN, bool kElect>
-__device__ inline void resolve_pending(const SolveArgs &a, const int32_t *col, unsigned long long *g) {
+template <int kN, bool kElect, typename T>
+__device__ inline void resolve_pending(const SolveArgs<T> &a, const int32_t *col, typename Val<T>::Bits *g) {
     bool any = false;
 #pragma unroll
     for (int c = 0; c < kN; ++c) any |= pending(a, col[c], g[c]);
@@ -174,8 +203,9 @@ __device__ inline void resolve_pending(const SolveArgs &a, const int32_t *col, u
 }
 
 // Value of a gathered term (after resolve_pending); 0 for pads.
-__device__ inline double term_value(int32_t k, unsigned long long v) {
-    return k == kPad ? 0.0 : __longlong_as_double((long long)v);
+template <typename T>
+__device__ inline T term_value(int32_t k, typename Val<T>::Bits v) {
+    return k == kPad ? T(0) : Val<T>::of(v);
 }
 
 template <int kCtrl>
@@ -185,11 +215,16 @@ __device__ inline double dpp_add(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), kCtrl, 0xf, 0xf, false);
     return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+template <int kCtrl>
+__device__ inline float dpp_add(float v) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+}
 
 // Sum over aligned groups of 2^lg lanes (every lane of a group gets the sum).
 // Groups up to 16 lanes stay in the ALU (DPP quad permutes, then the
 // half-row and row mirrors pair the two halves); 32 and 64 use permutes.
-__device__ inline double group_sum(double v, int lg) {
+template <typename T>
+__device__ inline T group_sum(T v, int lg) {
     if (lg >= 1) v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
     if (lg >= 2) v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
     if (lg >= 3) v = dpp_add<0x141>(v);  // row_half_mirror
@@ -202,7 +237,8 @@ __device__ inline double group_sum(double v, int lg) {
 // Descriptor of item i, fetched by a vector load (lane q < 4 reads word q)
 // so that it never waits behind LDS traffic, and unpacked into scalars only
 // when it is needed (one item later).
-__device__ inline int load_item(const SolveArgs &a, long long i, int lane) {
+template <typename T>
+__device__ inline int load_item(const SolveArgs<T> &a, long long i, int lane) {
     const long long idx = i < a.nitems ? i : 0;
     return reinterpret_cast<const int *>(a.items)[idx * 4 + (lane & 3)];
 }
@@ -216,26 +252,30 @@ __device__ inline int4 unpack_item(int w) {
 // Registers of one wide tile as seen by one lane.  They hold loads in
 // flight: nothing touches them until the tile is processed, so pads and
 // inactive lanes read a dummy address and are masked at use.
+template <typename T>
 struct Tile {
     int4 d;                     // {chunk offset, slot offset, chunks, nrows << 8 | log2 lanes per row}
     int32_t col[kRegChunks];    // term columns of this lane, raw
-    double val[kRegChunks];     // term coefficients, raw
+    T val[kRegChunks];          // term coefficients, raw
     int32_t row;                // row id of the lane's slot, raw
-    double diag;
+    T diag;
 };
 
 __device__ inline bool tile_active(const int4 d, int lane) { return (lane >> (d.w & 0xff)) < (d.w >> 8); }
 __device__ inline bool tile_lead(const int4 d, int lane) {
     return tile_active(d, lane) && (lane & ((1 << (d.w & 0xff)) - 1)) == 0;
 }
-__device__ inline int32_t tile_col(const Tile &T, int c, int lane) {
+template <typename V>
+__device__ inline int32_t tile_col(const Tile<V> &T, int c, int lane) {
     return tile_active(T.d, lane) && c < T.d.z ? T.col[c] : kPad;
 }
-__device__ inline double tile_val(const Tile &T, int c, int lane) {
-    return tile_active(T.d, lane) && c < T.d.z ? T.val[c] : 0.0;
+template <typename V>
+__device__ inline V tile_val(const Tile<V> &T, int c, int lane) {
+    return tile_active(T.d, lane) && c < T.d.z ? T.val[c] : V(0);
 }
 
-__device__ inline void load_tile(const SolveArgs &a, const int4 d, int lane, Tile &T) {
+template <typename V>
+__device__ inline void load_tile(const SolveArgs<V> &a, const int4 d, int lane, Tile<V> &T) {
     T.d = d;
     const bool active = tile_active(d, lane);
     const size_t base = (size_t)d.x * 64 + lane;
@@ -254,57 +294,75 @@ __device__ inline void load_tile(const SolveArgs &a, const int4 d, int lane, Til
 
 // One tile of a segment as seen by one lane, from load to finish.  As for
 // Tile, the loaded registers are left untouched until they are used.
+template <typename T> struct Four;
+template <> struct Four<double> { double2 a, b; };  // 4 coefficients in two 16-byte loads
+template <> struct Four<float> { float4 a; };       // ... or one
+
+template <typename T>
 struct SegSlot {
-    int4 col;                          // term columns
-    double2 v01, v23;                  // term coefficients
-    int2 rm;                           // {row (-1 if the lane finishes none), meta}
-    double diag;
-    unsigned long long g[kSegChunks];  // gathered b / external x (bits)
-    double bi;                         // b of the lane's row (meaningful where rm.x >= 0)
+    int4 col;                                  // term columns
+    Four<T> v;                                 // term coefficients
+    int2 rm;                                   // {row (-1 if the lane finishes none), meta}
+    T diag;
+    typename Val<T>::Bits g[kSegChunks];       // gathered b / external x (bits)
+    T bi;                                      // b of the lane's row (meaningful where rm.x >= 0)
 };
 
-__device__ inline int32_t seg_col(const SegSlot &S, int c) {
+template <typename T>
+__device__ inline int32_t seg_col(const SegSlot<T> &S, int c) {
     return c == 0 ? S.col.x : c == 1 ? S.col.y : c == 2 ? S.col.z : S.col.w;
 }
-__device__ inline double seg_val(const SegSlot &S, int c) {
-    return c == 0 ? S.v01.x : c == 1 ? S.v01.y : c == 2 ? S.v23.x : S.v23.y;
+__device__ inline double seg_val(const SegSlot<double> &S, int c) {
+    return c == 0 ? S.v.a.x : c == 1 ? S.v.a.y : c == 2 ? S.v.b.x : S.v.b.y;
+}
+__device__ inline float seg_val(const SegSlot<float> &S, int c) {
+    return c == 0 ? S.v.a.x : c == 1 ? S.v.a.y : c == 2 ? S.v.a.z : S.v.a.w;
 }
 
-__device__ inline void seg_load(const SolveArgs &a, long long st, int lane, SegSlot &S) {
-    static_assert(kSegChunks == 4, "segment tiles are fetched as int4 / 2 x double2 per lane");
+__device__ inline void load_four(const double *p, size_t ln, Four<double> &v) {
+    v.a = reinterpret_cast<const double2 *>(p)[2 * ln];
+    v.b = reinterpret_cast<const double2 *>(p)[2 * ln + 1];
+}
+__device__ inline void load_four(const float *p, size_t ln, Four<float> &v) {
+    v.a = reinterpret_cast<const float4 *>(p)[ln];
+}
+
+template <typename T>
+__device__ inline void seg_load(const SolveArgs<T> &a, long long st, int lane, SegSlot<T> &S) {
+    static_assert(kSegChunks == 4, "segment tiles are fetched as one int4 of columns per lane");
     const size_t ln = (size_t)st * 64 + lane;
     S.col = reinterpret_cast<const int4 *>(a.scol)[ln];
-    S.v01 = reinterpret_cast<const double2 *>(a.sval)[2 * ln];
-    S.v23 = reinterpret_cast<const double2 *>(a.sval)[2 * ln + 1];
+    load_four(a.sval, ln, S.v);
     S.rm = a.srow[ln];
     S.diag = a.sdiag[ln];
 }
 
-__device__ inline void seg_gather(const SolveArgs &a, SegSlot &S) {
+template <typename T>
+__device__ inline void seg_gather(const SolveArgs<T> &a, SegSlot<T> &S) {
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) S.g[c] = load_cached(gather_addr(a, seg_col(S, c)));
     S.bi = a.b[S.rm.x >= 0 ? S.rm.x : 0];
 }
 
-__device__ inline void seg_finish(const SolveArgs &a, SegSlot &S, double *ring) {
+template <typename T>
+__device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring) {
     int32_t col[kSegChunks];
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) col[c] = seg_col(S, c);
     resolve_pending<kSegChunks, false>(a, col, S.g);
-    double acc = 0.0;
+    T acc = T(0);
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) {
         const int32_t k = col[c];
-        const double v = k >= a.n ? ring[k - a.n] : term_value(k, S.g[c]);
+        const T v = k >= a.n ? ring[k - a.n] : term_value<T>(k, S.g[c]);
         acc = fma(seg_val(S, c), v, acc);
     }
     acc = group_sum(acc, __builtin_amdgcn_readfirstlane(S.rm.y) & 0xff);
     if (S.rm.x >= 0) {
-        const double xi = (S.bi + acc) / S.diag;
+        const T xi = (S.bi + acc) / S.diag;
         ring[S.rm.y >> 8] = xi;
-        __hip_atomic_store(reinterpret_cast<unsigned long long *>(a.x) + S.rm.x,
-                           (unsigned long long)__double_as_longlong(xi), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + S.rm.x, Val<T>::bits(xi),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -316,9 +374,10 @@ __device__ inline void seg_finish(const SolveArgs &a, SegSlot &S, double *ring) 
 // loads are harmless and keep the load count per step fixed).  The compiler
 // barriers keep every stage where it is written: left to itself the
 // scheduler sinks the prefetch loads down to their use.
-__device__ void run_segment(const SolveArgs &a, const int4 d, int lane, double *ring) {
+template <typename T>
+__device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ring) {
     const long long first = d.x, count = d.y, last = first + count - 1;
-    SegSlot S[kDepth];
+    SegSlot<T> S[kDepth];
 #pragma unroll
     for (int k = 0; k < kDepth; ++k) seg_load(a, min(first + k, last), lane, S[k]);
     asm volatile("" ::: "memory");
@@ -346,13 +405,15 @@ __device__ void run_segment(const SolveArgs &a, const int4 d, int lane, double *
 
 // ----------------------------------------------------------------- kernel --
 
-__global__ void __launch_bounds__(64) solve_tiles(SolveArgs a) {
-    __shared__ double ring[kRing];
+template <typename T>
+__global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
+    __shared__ T ring[kRing];
     const int lane = threadIdx.x;
     long long i = blockIdx.x;
     if (i >= a.nitems) return;
+    if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     int4 d = unpack_item(load_item(a, i, lane));
-    Tile cur;
+    Tile<T> cur;
     if (!is_segment(d)) load_tile(a, d, lane, cur);
     int wnext = load_item(a, i + a.waves, lane);  // raw descriptor of the next item
     for (;;) {
@@ -369,18 +430,18 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs a) {
         const int4 dnext = unpack_item(wnext);
         // 1. every gather of the current tile in flight
         int32_t col[kRegChunks];
-        unsigned long long g[kRegChunks];
+        typename Val<T>::Bits g[kRegChunks];
 #pragma unroll
         for (int c = 0; c < kRegChunks; ++c) {
             col[c] = tile_col(cur, c, lane);
             g[c] = load_cached(gather_addr(a, col[c]));
         }
         const bool lead = tile_lead(cur.d, lane);
-        const double bi = a.b[lead ? cur.row : 0];
+        const T bi = a.b[lead ? cur.row : 0];
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         // 2. the next tile's terms and the descriptor after it
-        Tile nxt;
+        Tile<T> nxt;
         const bool nwide = in < a.nitems && !is_segment(dnext);
         load_tile(a, nwide ? dnext : d, lane, nxt);
         const int wnn = load_item(a, inn, lane);
@@ -388,29 +449,28 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs a) {
         __builtin_amdgcn_sched_barrier(0);
         // 3. wait for the gathers, accumulate
         resolve_pending<kRegChunks, true>(a, col, g);
-        double acc = 0.0;
+        T acc = T(0);
 #pragma unroll
-        for (int c = 0; c < kRegChunks; ++c) acc = fma(tile_val(cur, c, lane), term_value(col[c], g[c]), acc);
+        for (int c = 0; c < kRegChunks; ++c) acc = fma(tile_val(cur, c, lane), term_value<T>(col[c], g[c]), acc);
         // 4. rows longer than the register chunks: stream the rest
         if (cur.d.z > kRegChunks) {
             if (tile_active(cur.d, lane)) {
                 const size_t base = (size_t)cur.d.x * 64 + lane;
                 for (int c = kRegChunks; c < cur.d.z; ++c) {
                     const int32_t k = a.tcol[base + (size_t)c * 64];
-                    const double v = a.tval[base + (size_t)c * 64];
-                    unsigned long long gv = load_cached(gather_addr(a, k));
+                    const T v = a.tval[base + (size_t)c * 64];
+                    typename Val<T>::Bits gv = load_cached(gather_addr(a, k));
                     if (pending(a, k, gv)) gv = wait_slow(a.x, k, a.ws, a.wait_limit);
-                    acc = fma(v, term_value(k, gv), acc);
+                    acc = fma(v, term_value<T>(k, gv), acc);
                 }
             }
         }
         // 5. row sums across the row's lanes, then x_i
         acc = group_sum(acc, cur.d.w & 0xff);
         if (lead) {
-            const double xi = (bi + acc) / cur.diag;
-            __hip_atomic_store(reinterpret_cast<unsigned long long *>(a.x) + cur.row,
-                               (unsigned long long)__double_as_longlong(xi), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            const T xi = (bi + acc) / cur.diag;
+            __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + cur.row, Val<T>::bits(xi),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (in >= a.nitems) break;
         cur = nxt;
@@ -420,6 +480,154 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs a) {
     }
 }
 
+// ------------------------------------------------------------ refinement --
+//
+// Mixed-precision iterative refinement for plans stored in FP32: with x = 0
+// and r = b, each step solves L d = r in FP32 with the schedule above,
+// updates x += d in FP64 and recomputes r = b - L x in FP64 from the
+// caller's FP64 matrix (one SpMV, a thread per entry of x).  The step's
+// largest correction, relative to max(|x_i|, 1e-3 max|x|), is reduced on the
+// device; once it is <= tol every later kernel of the call returns at once,
+// so the host enqueues a fixed sequence and never waits.
+
+constexpr int kRefBlock = 256;
+constexpr int kRefGrid = 2048;
+
+__device__ inline double block_max(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < kRefBlock / 64; ++k) v = fmax(v, red[k]);
+    return v;  // meaningful in thread 0
+}
+
+__device__ inline void atomic_max_nonneg(unsigned long long *p, double v) {
+    // non-negative doubles order like their bit patterns
+    __hip_atomic_fetch_max(p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline bool refine_done(const sptrsv::Workspace *ws) {
+    return __hip_atomic_load(&ws->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+// x = 0, r32 = b rounded, d32 = not ready; clears the refinement words.
+__global__ void __launch_bounds__(kRefBlock) refine_init(const double *__restrict__ b, double *__restrict__ x,
+                                                         float *__restrict__ r32, unsigned *__restrict__ d32,
+                                                         sptrsv::Workspace *ws, int32_t n) {
+    const int32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid == 0) {
+        ws->done = 0u;
+        ws->iters = 0u;
+    }
+    if (tid < sptrsv::kMaxRefine) {
+        ws->xmax[tid] = 0ull;
+        ws->ratio[tid] = 0ull;
+    }
+    for (int32_t i = tid; i < n; i += gridDim.x * blockDim.x) {
+        x[i] = 0.0;
+        r32[i] = (float)b[i];
+        d32[i] = Val<float>::kNotReady;
+    }
+}
+
+// x += d; per-step max |x| and the step's relative correction (against the
+// scale of the step before; the first step replaces x = 0 and is never final).
+__global__ void __launch_bounds__(kRefBlock) refine_update(double *__restrict__ x, const float *__restrict__ d32,
+                                                           sptrsv::Workspace *ws, int32_t n, int t) {
+    __shared__ double red[kRefBlock / 64];
+    if (refine_done(ws)) return;
+    const double floor_ = t > 0 ? 1e-3 * __longlong_as_double((long long)ws->xmax[t - 1]) : 0.0;
+    double xm = 0.0, rm = 0.0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double d = (double)d32[i];
+        const double xi = x[i] + d;
+        x[i] = xi;
+        xm = fmax(xm, fabs(xi));
+        // a NaN correction (a failed wait) counts as infinite: never converged
+        rm = fmax(rm, t > 0 && d == d ? fabs(d) / fmax(fabs(xi), floor_) : __builtin_inf());
+    }
+    xm = block_max(xm, red);
+    __syncthreads();
+    rm = block_max(rm, red);
+    if (threadIdx.x == 0) {
+        atomic_max_nonneg(&ws->xmax[t], xm);
+        atomic_max_nonneg(&ws->ratio[t], rm);
+        if (blockIdx.x == 0) __hip_atomic_store(&ws->iters, (unsigned)(t + 1), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// After step t: converged if its correction is <= tol (every block reads the
+// same word and block 0 raises the flag), else r = b - L x in FP64, rounded
+// to FP32 for the next correction, and d32 reset to not ready.
+__global__ void __launch_bounds__(kRefBlock) refine_residual(const int4 *__restrict__ sys, int32_t nsys,
+                                                             const int32_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ col,
+                                                             const double *__restrict__ val,
+                                                             const double *__restrict__ b,
+                                                             const double *__restrict__ x, float *__restrict__ r32,
+                                                             unsigned *__restrict__ d32, sptrsv::Workspace *ws,
+                                                             int32_t n, int t, double tol) {
+    if (refine_done(ws)) return;
+    const double ratio = __longlong_as_double((long long)ws->ratio[t]);
+    if (ratio <= tol) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            __hip_atomic_store(&ws->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        // system holding device index i: the last with base <= i
+        int lo = 0, hi = nsys - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sys[mid].x <= i) lo = mid; else hi = mid - 1;
+        }
+        const int4 S = sys[lo];
+        const int32_t rel = i - S.x, row = S.w + rel / S.z, c = rel % S.z;
+        double acc = b[i];
+        for (int32_t q = rp[row]; q < rp[row + 1]; ++q) acc = fma(-val[q], x[col[q] + c], acc);
+        r32[i] = (float)acc;
+        d32[i] = Val<float>::kNotReady;
+    }
+}
+
+template <typename T>
+SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n, int64_t nitems,
+                        int waves, uint64_t wait_limit, const void *b, void *x, const unsigned *skip) {
+    SolveArgs<T> a;
+    a.items = reinterpret_cast<const int4 *>(dev + lay->tiles);
+    a.rows = reinterpret_cast<const int32_t *>(dev + lay->rows);
+    a.diag = reinterpret_cast<const T *>(dev + lay->diag);
+    a.tcol = reinterpret_cast<const int32_t *>(dev + lay->tcol);
+    a.tval = reinterpret_cast<const T *>(dev + lay->tval);
+    a.scol = reinterpret_cast<const int32_t *>(dev + lay->scol);
+    a.sval = reinterpret_cast<const T *>(dev + lay->sval);
+    a.srow = reinterpret_cast<const int2 *>(dev + lay->srow);
+    a.sdiag = reinterpret_cast<const T *>(dev + lay->sdiag);
+    a.ws = reinterpret_cast<sptrsv::Workspace *>(const_cast<unsigned char *>(dev) + lay->workspace);
+    a.skip = skip;
+    a.b = static_cast<const T *>(b);
+    a.x = static_cast<T *>(x);
+    a.nitems = nitems;
+    a.waves = waves;
+    a.wait_limit = wait_limit;
+    a.n = n;
+    return a;
+}
+
+template <typename T>
+hipError_t launch_tiles(SolveArgs<T> a, int waves, hipStream_t s) {
+    void *args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(solve_tiles<T>), dim3(waves), dim3(64),
+                                      args, 0, s);
+}
+
+int fill_blocks(int32_t n) { return (int)std::min<int64_t>(2048, ((int64_t)n + 255) / 256); }
+
 }  // namespace
 
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
@@ -428,40 +636,61 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
     if (e != hipSuccess) return (int)e;
     e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return (int)e;
-    int blocks = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, solve_tiles, 64, 0);
+    // the FP64 instance holds the larger LDS ring, so it bounds residency
+    int b64 = 0, b32 = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, solve_tiles<double>, 64, 0);
     if (e != hipSuccess) return (int)e;
-    *max_waves_per_cu = blocks;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, solve_tiles<float>, 64, 0);
+    if (e != hipSuccess) return (int)e;
+    *max_waves_per_cu = std::min(b64, b32);
     return 0;
 }
 
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
-                                   int64_t nitems, int waves, uint64_t wait_limit, const double *b,
-                                   double *x, void *stream) {
+                                   int64_t nitems, int waves, uint64_t wait_limit, const void *b, void *x,
+                                   void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int fill_blocks = (int)std::min<int64_t>(2048, ((int64_t)n + 255) / 256);
-    hipLaunchKernelGGL(fill_not_ready, dim3(fill_blocks), dim3(256), 0, s,
-                       reinterpret_cast<unsigned long long *>(x), n);
+    hipError_t e;
+    if (lay->value_bytes == 4) {
+        hipLaunchKernelGGL(fill_not_ready<float>, dim3(fill_blocks(n)), dim3(256), 0, s,
+                           static_cast<unsigned *>(x), n);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        e = launch_tiles(solve_args<float>(dev, lay, n, nitems, waves, wait_limit, b, x, nullptr), waves, s);
+    } else {
+        hipLaunchKernelGGL(fill_not_ready<double>, dim3(fill_blocks(n)), dim3(256), 0, s,
+                           static_cast<unsigned long long *>(x), n);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        e = launch_tiles(solve_args<double>(dev, lay, n, nitems, waves, wait_limit, b, x, nullptr), waves, s);
+    }
+    return (int)e;
+}
+
+extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
+                                     int64_t nitems, int waves, uint64_t wait_limit, const double *b,
+                                     double *x, int iterations, double tol, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char *d = const_cast<unsigned char *>(dev);
+    sptrsv::Workspace *ws = reinterpret_cast<sptrsv::Workspace *>(d + lay->workspace);
+    float *r32 = reinterpret_cast<float *>(d + lay->r32);
+    float *d32 = reinterpret_cast<float *>(d + lay->d32);
+    const int grid = (int)std::min<int64_t>(kRefGrid, ((int64_t)n + kRefBlock - 1) / kRefBlock);
+    hipLaunchKernelGGL(refine_init, dim3(std::max(grid, 1)), dim3(kRefBlock), 0, s, b, x, r32,
+                       reinterpret_cast<unsigned *>(d32), ws, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
-    SolveArgs a;
-    a.items = reinterpret_cast<const int4 *>(dev + lay->tiles);
-    a.rows = reinterpret_cast<const int32_t *>(dev + lay->rows);
-    a.diag = reinterpret_cast<const double *>(dev + lay->diag);
-    a.tcol = reinterpret_cast<const int32_t *>(dev + lay->tcol);
-    a.tval = reinterpret_cast<const double *>(dev + lay->tval);
-    a.scol = reinterpret_cast<const int32_t *>(dev + lay->scol);
-    a.sval = reinterpret_cast<const double *>(dev + lay->sval);
-    a.srow = reinterpret_cast<const int2 *>(dev + lay->srow);
-    a.sdiag = reinterpret_cast<const double *>(dev + lay->sdiag);
-    a.ws = reinterpret_cast<sptrsv::Workspace *>(const_cast<unsigned char *>(dev) + lay->workspace);
-    a.b = b;
-    a.x = x;
-    a.nitems = nitems;
-    a.waves = waves;
-    a.wait_limit = wait_limit;
-    a.n = n;
-    void *args[] = {&a};
-    return (int)hipLaunchCooperativeKernel(reinterpret_cast<const void *>(solve_tiles), dim3(waves),
-                                           dim3(64), args, 0, s);
+    const SolveArgs<float> a = solve_args<float>(dev, lay, n, nitems, waves, wait_limit, r32, d32, &ws->done);
+    for (int t = 0; t < iterations; ++t) {
+        if ((e = launch_tiles(a, waves, s)) != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(refine_update, dim3(grid), dim3(kRefBlock), 0, s, x, d32, ws, n, t);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        if (t + 1 == iterations) break;
+        hipLaunchKernelGGL(refine_residual, dim3(grid), dim3(kRefBlock), 0, s,
+                           reinterpret_cast<const int4 *>(dev + lay->sys), lay->nsys,
+                           reinterpret_cast<const int32_t *>(dev + lay->res_rp),
+                           reinterpret_cast<const int32_t *>(dev + lay->res_col),
+                           reinterpret_cast<const double *>(dev + lay->res_val), b, x, r32,
+                           reinterpret_cast<unsigned *>(d32), ws, n, t, tol);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+    }
+    return 0;
 }

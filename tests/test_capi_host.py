@@ -26,12 +26,13 @@ def declared_functions():
     with open(os.path.join(ROOT, "include", "sptrsv.h")) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sptrsv_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sptrsv_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_exports_every_declared_symbol(sp):
     names = declared_functions()
     assert "sptrsv_solve" in names and "sptrsv_analyse" in names and len(names) >= 15
+    assert "sptrsv_solve_fp32" in names and "sptrsv_solve_refined" in names
     lib = ctypes.CDLL(sp.library_path())
     for name in names:
         assert hasattr(lib, name), name
@@ -306,3 +307,47 @@ def test_batch_errors(sp):
     assert e.value.status == "ERR_DIAG" and "system 1" in str(e.value)
     empty = sp.Plan.batch([])
     assert empty.info()["n"] == 0
+
+
+# ------------------------------------------------------- FP32 storage --
+
+def test_fp32_plan_keeps_the_schedule(sp):
+    """Storing the device image in FP32 changes the value type only: levels,
+    stages, rewritten structure and values (FP64 on the host) are those of
+    the FP64 plan, the precision survives a rewrite, and the byte counts
+    follow the value size."""
+    s = wl.powerlaw(20000, 600, seed=6)
+    p64 = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", max_depth=8)
+    p32 = sp.Plan(s.row_ptr, s.col_idx, s.val).set_precision(32).rewrite("threshold", max_depth=8)
+    i64, i32 = p64.info(), p32.info()
+    assert i64["precision"] == 64 and i32["precision"] == 32
+    for k in ("n", "levels", "stages", "levels_rw", "nnz", "nnz_rw", "nnz_m", "flops", "flops_rw", "tiles"):
+        assert i64[k] == i32[k], k
+    n = i64["n"]
+    assert i32["bytes"] == 8 * i32["nnz"] + 16 * n
+    assert i32["bytes_rw"] == 8 * (i32["nnz_rw"] + i32["nnz_m"]) + 16 * n
+    assert i64["bytes"] == 12 * i64["nnz"] + 24 * n
+    assert np.array_equal(p64.levels(1), p32.levels(1))
+    for a, b in zip(p64.export()[0] + p64.export()[1], p32.export()[0] + p32.export()[1]):
+        assert np.array_equal(a, b)
+    # the FP32 image carries the FP64 residual matrix and two FP32 vectors
+    assert i32["device_bytes"] > 12 * i32["nnz"] + 8 * n
+    p32.set_precision(64)
+    assert p32.info()["device_bytes"] == i64["device_bytes"]
+
+
+def test_fp32_errors_without_gpu(sp):
+    lib = sp.load()
+    s = wl.stencil2d(4, seed=0)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    assert sp.STATUS[lib.sptrsv_set_precision(plan._h, 16)] == "ERR_ARG"
+    assert sp.STATUS[lib.sptrsv_set_precision(None, 32)] == "ERR_ARG"
+    assert sp.STATUS[lib.sptrsv_solve_fp32(plan._h, None, None, None)] == "ERR_STATE"
+    assert sp.STATUS[lib.sptrsv_solve_refined(plan._h, None, None, 0, 0.0, None)] == "ERR_ARG"
+    assert sp.STATUS[lib.sptrsv_solve_refined(plan._h, None, None, 17, 0.0, None)] == "ERR_ARG"
+    assert sp.STATUS[lib.sptrsv_solve_refined(plan._h, None, None, 4, float("nan"), None)] == "ERR_ARG"
+    assert sp.STATUS[lib.sptrsv_solve_refined(plan._h, None, None, 4, 1e-13, None)] == "ERR_STATE"
+    it, corr = ctypes.c_int32(), ctypes.c_double()
+    assert sp.STATUS[lib.sptrsv_refine_stats(plan._h, None, ctypes.byref(it), ctypes.byref(corr))] == "ERR_STATE"
+    plan.set_precision(32)
+    assert sp.STATUS[lib.sptrsv_solve(plan._h, None, None, None)] == "ERR_STATE"

@@ -39,7 +39,7 @@ import numpy as np
 __all__ = [
     "System", "assemble", "stencil2d", "stencil3d", "banded", "powerlaw",
     "random_lower", "bidiagonal", "diagonal", "from_pairs", "transpose", "batch_corpus", "config",
-    "CONFIGS", "rhs",
+    "CONFIGS", "rhs", "fp32_valued",
 ]
 
 
@@ -292,6 +292,16 @@ def batch_corpus(count: int = 64, nmin: int = 1_000, nmax: int = 200_000, ks=(1,
 
 # ------------------------------------------------------ named workloads --
 
+def fp32_valued(s: System, k: int = 1, b_seed: int | None = None) -> System:
+    """The same structure with every value rounded to the nearest FP32 (ties
+    to even) and held in FP64: that FP32-valued matrix is the problem, so an
+    FP32 copy of it is exact.  With ``b_seed``, ``k`` new right-hand sides
+    are drawn from ``default_rng(b_seed)``; else ``s.b`` is kept."""
+    val = s.val.astype(np.float32).astype(np.float64)
+    b = s.b if b_seed is None else rhs(s.n, np.random.default_rng(b_seed), k)
+    return System(s.name + "_fp32", s.row_ptr, s.col_idx, val, b)
+
+
 CONFIGS = {
     # small workload: the oracle finishes it in milliseconds
     "stencil2d_100": lambda: stencil2d(100, seed=0),
@@ -299,6 +309,8 @@ CONFIGS = {
     "stencil3d_128": lambda: stencil3d(128, seed=1),
     "banded_1m": lambda: banded(1_000_000, 200, 8, 24, seed=2),
     "powerlaw_4m": lambda: powerlaw(4_000_000, 20_000, seed=3),
+    # precision workload: the power-law matrix with FP32 values, 8 right-hand sides
+    "powerlaw_4m_fp32_k8": lambda: fp32_valued(powerlaw(4_000_000, 20_000, seed=3), k=8, b_seed=5),
 }
 
 
