@@ -73,13 +73,24 @@ typedef enum {
  *                            absorbed levels stay <= floor(max_fill * nnz(L)),
  *                            and nnz(L') + nnz(M) stays <= max_entries;
  *   SPTRSV_POLICY_EXPLICIT   absorb[l] != 0 (l < absorb_len) and
- *                            nnz(L') + nnz(M) stays <= max_entries.
+ *                            nnz(L') + nnz(M) stays <= max_entries;
+ *   SPTRSV_POLICY_LEARNED    the stage holds fewer than max_depth levels, the
+ *                            budgets of THRESHOLD hold (max_fill,
+ *                            max_entries; max_width is ignored), and the
+ *                            cost model `model` (see sptrsv_mlp_forward)
+ *                            predicts that merging l into the stage adds less
+ *                            time than l costs as a stage of its own.  The
+ *                            model maps the shape of a group of rows
+ *                            (sptrsv_plan_level_features) to the log of its
+ *                            time in microseconds; it runs on the current
+ *                            device, once or twice per level, during the call.
  * Entries added by absorbing l: over its rows, (x-terms + b-terms after
  * rewriting) - (off-diagonals before), counted symbolically. */
 enum {
     SPTRSV_POLICY_NONE = 0,
     SPTRSV_POLICY_THRESHOLD = 1,
-    SPTRSV_POLICY_EXPLICIT = 2
+    SPTRSV_POLICY_EXPLICIT = 2,
+    SPTRSV_POLICY_LEARNED = 3
 };
 
 typedef struct {
@@ -91,10 +102,12 @@ typedef struct {
     const uint8_t *absorb;  /* host, absorb_len bytes; EXPLICIT only (may be NULL
                                when absorb_len == 0); read during the call only */
     int32_t absorb_len;     /* >= 0 */
+    const float *model;     /* LEARNED only: device, SPTRSV_MLP_PARAMS floats; read
+                               during the call only */
 } sptrsv_policy;
 
 /* Fills *p with THRESHOLD, max_width 4, max_depth 64, max_fill 0.25,
- * max_entries INT32_MAX, no mask. */
+ * max_entries INT32_MAX, no mask, no model. */
 void sptrsv_policy_default(sptrsv_policy *p);
 
 /* Matrix analysis (Sec. IV; DAG and level sets of Sec. II).  Validates and
@@ -128,10 +141,13 @@ sptrsv_status sptrsv_analyse_upper(int32_t n, const int32_t *row_ptr, const int3
  * systems interleaved) handles every system and every right-hand side.
  * sptrsv_solve then takes b and x as the concatenation, in order j = 0..,
  * of row-major n[j] x k[j] blocks (entry (i, c) of system j at
- * base_j + i*k[j] + c, base_j = sum_{j' < j} n[j'] k[j']).  Introspection
- * reports the union (copy c of system j occupies union rows
- * base_j + c*n[j] .. + n[j]).  Errors: as sptrsv_analyse (message names the
- * system), ARG (k < 1, null arrays), OVERFLOW (union beyond int32). */
+ * base_j + i*k[j] + c, base_j = sum_{j' < j} n[j'] k[j']).  The union
+ * is numbered the same way: copy c of row i of system j is union row
+ * base_j + i*k[j] + c, so the copies of a row share its level and sit side by
+ * side in the schedule, and the gathers of a term for all right-hand sides
+ * read one contiguous run of x.  Introspection reports the union.  Errors: as
+ * sptrsv_analyse (message names the system), ARG (k < 1, null arrays),
+ * OVERFLOW (union beyond int32). */
 sptrsv_status sptrsv_analyse_batch(int32_t count, const int32_t *n, const int32_t *const *row_ptr,
                                    const int32_t *const *col_idx, const double *const *val,
                                    const int32_t *k, sptrsv_plan *out);
@@ -190,9 +206,12 @@ sptrsv_status sptrsv_solve_fp32(sptrsv_plan plan, const float *b, float *x, void
  * extension; the paper's solve is a single pass): b and x are device arrays
  * of n doubles.  With x = 0 and r = b, each step solves L d = r (r rounded to
  * FP32) with the FP32 schedule, updates x += d in FP64 and recomputes
- * r = b - L x in FP64 with the caller's FP64 matrix.  After step t >= 1 the
- * largest correction |d_i| / max(|x_i|, 1e-3 max_j |x_j|) is compared with
- * tol on the device; once it is <= tol the remaining steps do nothing.
+ * r = b - L x in FP64 with the caller's FP64 matrix.  Step t's correction
+ * c_t = max_i |d_i| / max(|x_i|, 1e-3 max_j |x_j|) (step 0's counts as
+ * infinite) measures the error before the step; the error after it is
+ * estimated as c_t * min(1, c_t / c_{t-1}) from step 2 on (linear
+ * convergence at the observed rate), as c_1 at step 1.  Once the estimate
+ * is <= tol, checked on the device, the remaining steps do nothing.
  * At most `iterations` (1..16) steps; everything is enqueued on stream
  * without waiting.  sptrsv_refine_stats reports the steps taken.  Errors: as
  * sptrsv_solve_fp32; ARG (iterations out of range, tol < 0 or NaN). */
@@ -200,8 +219,8 @@ sptrsv_status sptrsv_solve_refined(sptrsv_plan plan, const double *b, double *x,
                                    double tol, void *stream);
 
 /* Waits for stream, then reports the last refinement: *iterations = steps
- * applied, *correction = the relative correction of the last step applied
- * (+inf after a single step).  Errors: ARG, STATE (not uploaded, or FP64
+ * applied, *correction = c_t of the last step applied (+inf after a single
+ * step).  Errors: ARG, STATE (not uploaded, or FP64
  * plan), HIP. */
 sptrsv_status sptrsv_refine_stats(sptrsv_plan plan, void *stream, int32_t *iterations,
                                   double *correction);
@@ -244,6 +263,8 @@ typedef struct {
     int64_t device_bytes;/* size of the device image + workspace */
     int64_t tiles;       /* 64-lane work tiles in the device schedule */
     int32_t precision;   /* 64 or 32: value type of the device image */
+    int64_t seg_tiles;   /* tiles inside segments (runs of narrow levels one
+                            wave executes in order) */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 
@@ -267,6 +288,66 @@ sptrsv_status sptrsv_plan_schedule(sptrsv_plan plan, int32_t *level_ptr, int32_t
 sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_col,
                                  double *lp_val, int64_t *m_ptr, int32_t *m_col,
                                  double *m_val);
+
+/* ---- Timing and the learned cost model ----------------------------------
+ *
+ * The paper picks the levels to rewrite by hand (Sec. IV, V).  The LEARNED
+ * policy picks them with a small cost model trained on solve times that the
+ * library itself measures: an instrumented solve stamps the GPU real-time
+ * clock (100 MHz) as each unit of work completes, sptrsv_plan_stamp_levels
+ * maps the stamps to executed levels, sptrsv_plan_level_features gives each
+ * executed level's shape, and the model (a 6-64-64-1 perceptron in FP32,
+ * tanh hidden layers) is trained with the kernels below.  Parameter vector,
+ * SPTRSV_MLP_PARAMS floats: W1[64][6], b1[64], W2[64][64], b2[64], w3[64], b3;
+ * the output is w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3. */
+#define SPTRSV_MLP_INPUTS 6
+#define SPTRSV_MLP_PARAMS 4673
+
+/* As sptrsv_solve (FP64 plans) with an instrumented kernel that also writes
+ * stamps (device, tiles + seg_tiles + 1 uint64, owned by the caller):
+ * stamps[u] = clock when unit u completed (units: the tiles of the schedule,
+ * then the segment tiles), stamps[tiles + seg_tiles] = clock when the grid
+ * started.  Slower than sptrsv_solve by a store per unit.  Errors: as
+ * sptrsv_solve; ARG (stamps NULL); STATE (FP32 plan). */
+sptrsv_status sptrsv_solve_stamped(sptrsv_plan plan, const double *b, double *x, uint64_t *stamps,
+                                   void *stream);
+
+/* Executed level (of L') of the rows each stamp unit finishes (host int32,
+ * tiles + seg_tiles entries); -1 for units that finish no level by
+ * themselves (whole segments, padding tiles).  A level's completion time is
+ * the latest stamp among its units. */
+sptrsv_status sptrsv_plan_stamp_levels(sptrsv_plan plan, int32_t *level);
+
+/* Shape of every executed level as the model's inputs (host float
+ * [levels_rw][SPTRSV_MLP_INPUTS]): log2(1 + rows) / 16, log2(1 + entries) / 24,
+ * entries added by rewriting per entry of L (capped at 16) / 4,
+ * log2(1 + longest row) / 8, entries per row (capped at 256) / 16,
+ * log2(original levels merged) / 8; entries of a row = x-terms + b-terms +
+ * diagonal. */
+sptrsv_status sptrsv_plan_level_features(sptrsv_plan plan, float *features);
+
+/* y[s] = model(x[s]) for s < m (device arrays: params SPTRSV_MLP_PARAMS
+ * floats, x [m][SPTRSV_MLP_INPUTS], y [m]); enqueued on stream.  Errors: ARG. */
+sptrsv_status sptrsv_mlp_forward(const float *params, const float *x, float *y, int32_t m, void *stream);
+
+/* Bytes of the device workspace sptrsv_mlp_grad needs for m samples. */
+sptrsv_status sptrsv_mlp_grad_workspace(int32_t m, size_t *bytes);
+
+/* Gradient of the mean squared error (1/m) sum_s (model(x[s]) - t[s])^2 with
+ * respect to the parameters, by back-propagation (device: grad
+ * SPTRSV_MLP_PARAMS floats, loss one float or NULL, workspace as sized by
+ * sptrsv_mlp_grad_workspace); sums run in a fixed order, so the result is
+ * deterministic.  Enqueued on stream.  Errors: ARG (m < 1, null, workspace
+ * too small), HIP. */
+sptrsv_status sptrsv_mlp_grad(const float *params, const float *x, const float *t, int32_t m,
+                              float *grad, float *loss, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/* One Adam step (Kingma and Ba, 2015) on params with moment buffers m1, m2
+ * (device, SPTRSV_MLP_PARAMS floats each, zero before step 1); step >= 1 is
+ * the step number for the bias corrections.  Errors: ARG, HIP. */
+sptrsv_status sptrsv_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step,
+                              float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Releases the plan (host memory only; the caller frees its device buffer
  * after the last solve that uses it has finished).  NULL is ignored. */

@@ -18,14 +18,17 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "Policy", "SptrsvError", "library_path", "load", "STATUS"]
+__all__ = ["Plan", "Policy", "SptrsvError", "library_path", "load", "STATUS", "mlp_forward",
+           "mlp_grad", "mlp_adam"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CSR", 3: "ERR_DIAG", 4: "ERR_OVERFLOW",
           5: "ERR_OOM", 6: "ERR_HIP", 7: "ERR_STATE", 8: "ERR_TIMEOUT"}
-KIND = {"none": 0, "threshold": 1, "explicit": 2}
+KIND = {"none": 0, "threshold": 1, "explicit": 2, "learned": 3}
+MLP_INPUTS = 6
+MLP_PARAMS = 4673
 INT32_MAX = 2**31 - 1
 
 
@@ -42,7 +45,7 @@ class Policy(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("max_width", ctypes.c_int32),
                 ("max_depth", ctypes.c_int32), ("max_fill", ctypes.c_double),
                 ("max_entries", ctypes.c_int64), ("absorb", ctypes.c_void_p),
-                ("absorb_len", ctypes.c_int32)]
+                ("absorb_len", ctypes.c_int32), ("model", ctypes.c_void_p)]
 
 
 class _Info(ctypes.Structure):
@@ -51,7 +54,7 @@ class _Info(ctypes.Structure):
                 ("nnz_m", ctypes.c_int64), ("flops", ctypes.c_int64), ("flops_rw", ctypes.c_int64),
                 ("bytes", ctypes.c_int64), ("bytes_rw", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("seg_tiles", ctypes.c_int64)]
 
 
 _lib = None
@@ -85,6 +88,14 @@ def load():
         "sptrsv_solve_refined": (S, [P, P, P, I32, ctypes.c_double, P]),
         "sptrsv_refine_stats": (S, [P, P, P, P]),
         "sptrsv_set_precision": (S, [P, I32]),
+        "sptrsv_solve_stamped": (S, [P, P, P, P, P]),
+        "sptrsv_plan_stamp_levels": (S, [P, P]),
+        "sptrsv_plan_level_features": (S, [P, P]),
+        "sptrsv_mlp_forward": (S, [P, P, P, I32, P]),
+        "sptrsv_mlp_grad_workspace": (S, [I32, P]),
+        "sptrsv_mlp_grad": (S, [P, P, P, I32, P, P, P, ctypes.c_size_t, P]),
+        "sptrsv_mlp_adam": (S, [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, P]),
         "sptrsv_check": (S, [P, P, P]),
         "sptrsv_set_wait_limit": (S, [P, U64]),
         "sptrsv_set_launch": (S, [P, I32]),
@@ -125,13 +136,15 @@ def _stream(stream):
 
 
 def make_policy(kind: str = "threshold", max_width: int = 4, max_depth: int = 64,
-                max_fill: float = 0.25, max_entries: int = INT32_MAX, absorb=None):
-    """A :class:`Policy` (and the mask array that must outlive the call)."""
+                max_fill: float = 0.25, max_entries: int = INT32_MAX, absorb=None, model=None):
+    """A :class:`Policy` (and the mask array that must outlive the call).
+    ``model``: a float32 CUDA tensor of MLP_PARAMS parameters (LEARNED)."""
     mask = None
     if absorb is not None:
         mask = np.ascontiguousarray(absorb, dtype=np.uint8)
     pol = Policy(KIND[kind], int(max_width), int(max_depth), float(max_fill), int(max_entries),
-                 None if mask is None else mask.ctypes.data, 0 if mask is None else mask.size)
+                 None if mask is None else mask.ctypes.data, 0 if mask is None else mask.size,
+                 None if model is None else model.data_ptr())
     return pol, mask
 
 
@@ -281,6 +294,24 @@ class Plan:
         _check(load().sptrsv_refine_stats(self._h, _stream(stream), ctypes.byref(it), ctypes.byref(corr)))
         return it.value, corr.value
 
+    def solve_stamped(self, b, x, stamps, stream=None):
+        """Instrumented solve: ``stamps`` an int64 CUDA tensor of
+        ``info()['tiles'] + info()['seg_tiles'] + 1`` entries."""
+        _check(load().sptrsv_solve_stamped(self._h, _ptr(b), _ptr(x), _ptr(stamps), _stream(stream)))
+        return x
+
+    def stamp_levels(self) -> np.ndarray:
+        i = self.info()
+        out = np.empty(i["tiles"] + i["seg_tiles"], dtype=np.int32)
+        _check(load().sptrsv_plan_stamp_levels(self._h, _ptr(out)))
+        return out
+
+    def level_features(self) -> np.ndarray:
+        nl = self.info()["levels_rw"]
+        out = np.empty((nl, MLP_INPUTS), dtype=np.float32)
+        _check(load().sptrsv_plan_level_features(self._h, _ptr(out)))
+        return out
+
     def check(self, stream=None) -> int:
         st = ctypes.c_int32()
         _check(load().sptrsv_check(self._h, _stream(stream), ctypes.byref(st)))
@@ -297,3 +328,41 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------- cost model --
+
+def mlp_forward(params, x, y=None, stream=None):
+    """y = model(x) for the rows of x (float32 CUDA tensors; x of shape
+    (m, MLP_INPUTS))."""
+    import torch
+    if y is None:
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(load().sptrsv_mlp_forward(_ptr(params), _ptr(x), _ptr(y), int(x.shape[0]), _stream(stream)))
+    return y
+
+
+def mlp_grad(params, x, t, grad=None, loss=None, workspace=None, stream=None):
+    """Gradient of the mean squared error of the model on (x, t); returns
+    (grad, loss) as CUDA tensors (loss a one-element tensor)."""
+    import torch
+    m = int(x.shape[0])
+    nb = ctypes.c_size_t()
+    _check(load().sptrsv_mlp_grad_workspace(m, ctypes.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(load().sptrsv_mlp_grad(_ptr(params), _ptr(x), _ptr(t), m, _ptr(grad), _ptr(loss),
+                                  _ptr(workspace), workspace.numel(), _stream(stream)))
+    return grad, loss
+
+
+def mlp_adam(params, grad, m1, m2, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, stream=None):
+    """One Adam step in place on params (float32 CUDA tensors)."""
+    _check(load().sptrsv_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(step), float(lr),
+                                  float(beta1), float(beta2), float(eps), _stream(stream)))
+    return params

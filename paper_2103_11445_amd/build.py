@@ -18,7 +18,7 @@ BUILD = os.path.join(PKG, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["analyse.cpp", "rewrite.cpp", "pack.cpp", "capi.cpp"]
-HIP_SOURCES = ["solve.hip"]
+HIP_SOURCES = ["solve.hip", "mlp.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra",
               "-D__HIP_PLATFORM_AMD__", f"-I{INCLUDE}", f"-I{CSRC}", f"-I{ROCM}/include"]

@@ -113,9 +113,12 @@ void analyse_upper(Plan &p, int32_t n, const int32_t *rp, const int32_t *ci, con
 
 // Many systems at once: matrix j (n_j rows) with k_j right-hand sides becomes
 // k_j copies of its block on the diagonal of one lower-triangular union, so a
-// single plan (and a single launch) solves all of them.  Copy c of block j,
-// row i, is union row base_j + c*n_j + i and lives at base_j + i*k_j + c in
-// the concatenation of the callers' row-major n_j x k_j blocks.
+// single plan (and a single launch) solves all of them.  The copies are
+// interleaved: copy c of row i of system j is union row base_j + i*k_j + c,
+// which is also where its b and x entries sit in the concatenation of the
+// callers' row-major n_j x k_j blocks.  The k_j copies of a row then share a
+// level and sit side by side in the device schedule, so the gathers of one
+// term for all right-hand sides touch one contiguous run of x.
 void analyse_batch(Plan &p, int32_t count, const int32_t *n, const int32_t *const *rp,
                    const int32_t *const *ci, const double *const *val, const int32_t *k) {
     if (count < 0) fail(SPTRSV_ERR_ARG, "count < 0");
@@ -136,25 +139,22 @@ void analyse_batch(Plan &p, int32_t count, const int32_t *n, const int32_t *cons
         fail(SPTRSV_ERR_OVERFLOW, "batch too large for int32 indexing");
     std::vector<int32_t> urp((size_t)rows + 1, 0), uci((size_t)nnz);
     std::vector<double> uval((size_t)nnz);
-    std::vector<int32_t> index((size_t)rows);
     int64_t r = 0, q = 0, base = 0;
     for (int32_t j = 0; j < count; ++j) {
-        for (int32_t c = 0; c < k[j]; ++c) {
-            const int64_t off = base + (int64_t)c * n[j];
-            for (int32_t i = 0; i < n[j]; ++i) {
+        const int64_t kj = k[j];
+        for (int32_t i = 0; i < n[j]; ++i) {
+            for (int64_t c = 0; c < kj; ++c) {
                 for (int32_t t = rp[j][i]; t < rp[j][i + 1]; ++t) {
-                    uci[(size_t)q] = (int32_t)(off + ci[j][t]);
+                    uci[(size_t)q] = (int32_t)(base + (int64_t)ci[j][t] * kj + c);
                     uval[(size_t)q] = val[j][t];
                     ++q;
                 }
-                index[(size_t)r] = (int32_t)(base + (int64_t)i * k[j] + c);
                 urp[(size_t)++r] = (int32_t)q;
             }
         }
-        base += (int64_t)n[j] * k[j];
+        base += (int64_t)n[j] * kj;
     }
     analyse(p, (int32_t)rows, urp.data(), uci.data(), uval.data());
-    p.dev_index = std::move(index);
     p.batch_count = count;
     p.sys_n.assign(n, n + count);
     p.sys_k.assign(k, k + count);

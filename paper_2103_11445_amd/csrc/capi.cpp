@@ -11,6 +11,7 @@
 #include <cstddef>
 #include <string>
 
+#include "features.hpp"
 #include "plan.hpp"
 
 struct sptrsv_plan_s : sptrsv::Plan {};
@@ -233,7 +234,7 @@ sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *s
         if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
         const int waves = launch_waves(*plan);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, plan->wait_limit, b, x, stream);
+                                          plan->ntiles, waves, plan->wait_limit, b, x, nullptr, 0, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -244,7 +245,7 @@ sptrsv_status sptrsv_solve_fp32(sptrsv_plan plan, const float *b, float *x, void
         if (solve_args_ok(plan, b, x, 32, sizeof(float))) return SPTRSV_OK;
         const int waves = launch_waves(*plan);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, plan->wait_limit, b, x, stream);
+                                          plan->ntiles, waves, plan->wait_limit, b, x, nullptr, 0, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -322,7 +323,7 @@ sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, v
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
             const int le = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
-                                               plan->ntiles, waves, plan->wait_limit, b, x, cs);
+                                               plan->ntiles, waves, plan->wait_limit, b, x, nullptr, 0, cs);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(cs, &g);
             if (le != 0) {
@@ -396,6 +397,7 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->device_bytes = (int64_t)p.layout.total;
     o->tiles = p.ntiles;
     o->precision = p.precision;
+    o->seg_tiles = p.nseg_tiles;
     return SPTRSV_OK;
 }
 
@@ -433,6 +435,83 @@ sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_
     std::copy(p.m_ptr.begin(), p.m_ptr.end(), m_ptr);
     std::copy(p.m_col.begin(), p.m_col.end(), m_col);
     std::copy(p.m_val.begin(), p.m_val.end(), m_val);
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_solve_stamped(sptrsv_plan plan, const double *b, double *x, uint64_t *stamps, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
+        if (!stamps) return set_err(SPTRSV_ERR_ARG, "stamps is NULL");
+        const int waves = launch_waves(*plan);
+        const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
+                                          plan->ntiles, waves, plan->wait_limit, b, x,
+                                          reinterpret_cast<unsigned long long *>(stamps),
+                                          plan->ntiles + plan->nseg_tiles, stream);
+        if (e != 0) return hip_err((hipError_t)e, "kernel launch");
+        return SPTRSV_OK;
+    });
+}
+
+sptrsv_status sptrsv_plan_stamp_levels(sptrsv_plan plan, int32_t *level) {
+    if (!plan || (!level && !plan->stamp_level.empty())) return set_err(SPTRSV_ERR_ARG, "null argument");
+    std::copy(plan->stamp_level.begin(), plan->stamp_level.end(), level);
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_plan_level_features(sptrsv_plan plan, float *features) {
+    if (!plan || (!features && plan->nlev_rw > 0)) return set_err(SPTRSV_ERR_ARG, "null argument");
+    const sptrsv::Plan &p = *plan;
+    for (int32_t l = 0; l < p.nlev_rw; ++l) {
+        sptrsv::GroupShape g;
+        int32_t lo = INT32_MAX, hi = -1;
+        for (int32_t q = p.sched_ptr[(size_t)l]; q < p.sched_ptr[(size_t)l + 1]; ++q) {
+            const int32_t i = p.sched_rows[(size_t)q];
+            const int64_t len = (p.lp_ptr[(size_t)i + 1] - p.lp_ptr[(size_t)i]) +
+                                (p.m_ptr[(size_t)i + 1] - p.m_ptr[(size_t)i]);
+            ++g.rows;
+            g.terms += len;
+            g.orig += p.rp[(size_t)i + 1] - p.rp[(size_t)i];
+            g.maxlen = std::max(g.maxlen, len);
+            lo = std::min(lo, p.level[(size_t)i]);
+            hi = std::max(hi, p.level[(size_t)i]);
+        }
+        g.span = hi >= lo ? hi - lo + 1 : 1;
+        sptrsv::group_features(g, features + (size_t)l * sptrsv::kFeatures);
+    }
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_mlp_forward(const float *params, const float *x, float *y, int32_t m, void *stream) {
+    if (m < 0) return set_err(SPTRSV_ERR_ARG, "m < 0");
+    if (m == 0) return SPTRSV_OK;
+    if (!params || !x || !y) return set_err(SPTRSV_ERR_ARG, "null argument");
+    const int e = sptrsv_launch_mlp_forward(params, x, y, m, stream);
+    if (e != 0) return hip_err((hipError_t)e, "kernel launch");
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_mlp_grad_workspace(int32_t m, size_t *bytes) {
+    if (m < 1 || !bytes) return set_err(SPTRSV_ERR_ARG, "m < 1 or bytes NULL");
+    *bytes = sptrsv_launch_mlp_workspace(m);
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_mlp_grad(const float *params, const float *x, const float *t, int32_t m, float *grad,
+                              float *loss, void *workspace, size_t workspace_bytes, void *stream) {
+    if (m < 1) return set_err(SPTRSV_ERR_ARG, "m < 1");
+    if (!params || !x || !t || !grad || !workspace) return set_err(SPTRSV_ERR_ARG, "null argument");
+    if (workspace_bytes < sptrsv_launch_mlp_workspace(m)) return set_err(SPTRSV_ERR_ARG, "workspace too small");
+    const int e = sptrsv_launch_mlp_grad(params, x, t, m, grad, loss, workspace, stream);
+    if (e != 0) return hip_err((hipError_t)e, "kernel launch");
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step, float lr,
+                              float beta1, float beta2, float eps, void *stream) {
+    if (!params || !grad || !m1 || !m2) return set_err(SPTRSV_ERR_ARG, "null argument");
+    if (step < 1) return set_err(SPTRSV_ERR_ARG, "step < 1");
+    const int e = sptrsv_launch_mlp_adam(params, grad, m1, m2, step, lr, beta1, beta2, eps, stream);
+    if (e != 0) return hip_err((hipError_t)e, "kernel launch");
     return SPTRSV_OK;
 }
 

@@ -85,8 +85,8 @@ void pack(Plan &p) {
     // ---- order rows and cut items
     std::vector<int32_t> slot_row((size_t)n);
     struct Tile { int64_t chunk_off; int32_t row_off, nch, nrows, lg; };
-    struct SegTile { int32_t row_off, nrows, lg; };
-    struct Item { int kind; int64_t a, b; };  // wide: a = wide tile; seg: a = first seg tile, b = count
+    struct SegTile { int32_t row_off, nrows, lg, level; };
+    struct Item { int kind; int64_t a, b; int32_t level; };  // wide: a = wide tile; seg: a = first seg tile, b = count
     std::vector<Tile> tiles;
     std::vector<SegTile> stiles;
     std::vector<Item> items;
@@ -98,7 +98,7 @@ void pack(Plan &p) {
         const int32_t b0 = p.sched_ptr[(size_t)l], b1 = p.sched_ptr[(size_t)l + 1];
         if (in_seg[(size_t)l]) {
             if (l == 0 || !in_seg[(size_t)l - 1]) {
-                items.push_back({1, (int64_t)stiles.size(), 0});
+                items.push_back({1, (int64_t)stiles.size(), 0, -1});
                 ++nseg;
             }
             const int lg = seg_lg[(size_t)l];
@@ -108,7 +108,7 @@ void pack(Plan &p) {
                 seg_of_slot[(size_t)(slot + q - b0)] = nseg - 1;
             }
             for (int32_t s = slot; s < slot + (b1 - b0); s += per) {
-                stiles.push_back({s, std::min(per, slot + (b1 - b0) - s), lg});
+                stiles.push_back({s, std::min(per, slot + (b1 - b0) - s), lg, l});
                 items.back().b += 1;
             }
             slot += b1 - b0;
@@ -116,7 +116,7 @@ void pack(Plan &p) {
                 // pad the segment to a whole number of pipeline steps with
                 // empty tiles (no rows, no terms)
                 while (items.back().b % kSegDepth) {
-                    stiles.push_back({slot, 0, 0});
+                    stiles.push_back({slot, 0, 0, -1});
                     items.back().b += 1;
                 }
             }
@@ -143,7 +143,7 @@ void pack(Plan &p) {
                 int64_t mx = 0;
                 for (int32_t r = 0; r < nr; ++r) mx = std::max(mx, len[(size_t)slot_row[(size_t)(s + r)]]);
                 const int64_t nch = (mx + (1 << g) - 1) >> g;
-                items.push_back({0, (int64_t)tiles.size(), 0});
+                items.push_back({0, (int64_t)tiles.size(), 0, l});
                 tiles.push_back({nchunks, s, (int32_t)nch, nr, g});
                 nchunks += nch;
             }
@@ -193,10 +193,10 @@ void pack(Plan &p) {
     if (f32) {
         Ly.nsys = (int32_t)p.sys_n.size();
         for (size_t j = 0; j < p.sys_n.size(); ++j) {
-            const int32_t nj = p.sys_n[j];
-            const int64_t r0 = p.upper ? 0 : p.sys_base[j];
+            // a system's block of the union holds k identical copies
+            const int64_t nj = p.sys_n[j], kj = p.sys_k[j], r0 = p.sys_base[j];
             Ly.res_rows += nj;
-            Ly.res_nnz += nj ? (int64_t)p.rp[(size_t)(r0 + nj)] - p.rp[(size_t)r0] : 0;
+            Ly.res_nnz += ((int64_t)p.rp[(size_t)(r0 + nj * kj)] - p.rp[(size_t)r0]) / kj;
         }
         if (Ly.res_nnz > INT32_MAX) throw Error{SPTRSV_ERR_OVERFLOW, "residual matrix beyond int32 indexing"};
         Ly.sys = off;
@@ -231,12 +231,9 @@ void pack(Plan &p) {
     std::fill(tcol, tcol + nchunks * 64, kPad);
     std::fill(scol, scol + nst * kSegChunks * 64, kPad);
     for (int64_t q = 0; q < nst * 64; ++q) srow[2 * q] = -1;
-    // the device image speaks the caller's indices (reversed for upper input,
-    // mapped into the right-hand-side blocks for batched input)
-    auto orig = [&](int32_t i) {
-        if (!p.dev_index.empty()) return p.dev_index[(size_t)i];
-        return p.upper ? n - 1 - i : i;
-    };
+    // the device image speaks the caller's indices (reversed for upper
+    // input; a batched union is numbered like the callers' blocks already)
+    auto orig = [&](int32_t i) { return p.upper ? n - 1 - i : i; };
     for (int32_t s = 0; s < n; ++s) {
         const int32_t i = slot_row[(size_t)s];
         trow[s] = orig(i);
@@ -324,10 +321,11 @@ void pack(Plan &p) {
             sys[4 * j + 2] = kj;
             sys[4 * j + 3] = (int32_t)row;
             for (int32_t i = 0; i < nj; ++i) {
-                // plan row holding the caller's row i (copy 0 of a batched system)
-                const int64_t r = p.upper ? (int64_t)n - 1 - i : base + i;
+                // plan row holding the caller's row i (its copy 0 in a batch)
+                const int64_t r = p.upper ? (int64_t)n - 1 - i : base + (int64_t)i * kj;
                 for (int32_t t = p.rp[(size_t)r]; t < p.rp[(size_t)r + 1]; ++t) {
-                    const int64_t l = p.upper ? (int64_t)n - 1 - p.ci[(size_t)t] : p.ci[(size_t)t] - base;
+                    if (q >= Ly.res_nnz) throw Error{SPTRSV_ERR_STATE, "internal: residual matrix overflow"};
+                    const int64_t l = p.upper ? (int64_t)n - 1 - p.ci[(size_t)t] : (p.ci[(size_t)t] - base) / kj;
                     rcol[q] = (int32_t)(base + l * kj);
                     rval[q] = p.val[(size_t)t];
                     ++q;
@@ -335,7 +333,13 @@ void pack(Plan &p) {
                 rrp[++row] = (int32_t)q;
             }
         }
+        if (row != Ly.res_rows || q != Ly.res_nnz)
+            throw Error{SPTRSV_ERR_STATE, "internal: residual matrix size mismatch"};
     }
+    // executed level of every completion stamp of an instrumented solve
+    p.stamp_level.resize(items.size() + stiles.size());
+    for (size_t it = 0; it < items.size(); ++it) p.stamp_level[it] = items[it].level;
+    for (size_t st = 0; st < stiles.size(); ++st) p.stamp_level[items.size() + st] = stiles[st].level;
     p.ntiles = (int64_t)items.size();
     p.nchunks = nchunks;
     p.nseg = nseg;

@@ -78,10 +78,6 @@ struct Plan {
     // indices
     int32_t n = 0;
     bool upper = false;
-    // device index of each row when it is not the row itself (batched plans:
-    // the rows of a block-diagonal union map into the callers' row-major
-    // right-hand-side blocks); empty otherwise
-    std::vector<int32_t> dev_index;
     int32_t batch_count = 0;
     // the caller's systems as the plan holds them: rows, right-hand sides
     // and device base of each (one entry for an unbatched plan)
@@ -115,6 +111,10 @@ struct Plan {
     int64_t nchunks = 0;
     int32_t nseg = 0;        // segments
     int64_t nseg_tiles = 0;  // tiles inside segments
+    // executed level (of L') whose rows each item and each segment tile
+    // finish, -1 for segment items and padding tiles: the map of the
+    // completion stamps of an instrumented solve
+    std::vector<int32_t> stamp_level;
 
     // ---- device state
     void *dev = nullptr;
@@ -152,9 +152,20 @@ void pack(Plan &p);
 
 // solve.hip -- kernel launchers (return a hipError_t as int).  b and x are
 // double or float as lay->value_bytes says.
+// With stamps (FP64 plans only), the instrumented kernel also writes the
+// real-time clock (100 MHz) as every item and every segment tile completes
+// (slots [0, nitems) and nitems + segment tile), and its start at start_slot.
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay,
                                    int32_t n, int64_t nitems, int waves, uint64_t wait_limit,
-                                   const void *b, void *x, void *stream);
+                                   const void *b, void *x, unsigned long long *stamps, int64_t start_slot,
+                                   void *stream);
+// mlp.hip -- cost model kernels (FP32 parameter vector of 4673 floats)
+extern "C" size_t sptrsv_launch_mlp_workspace(int32_t m);
+extern "C" int sptrsv_launch_mlp_forward(const float *params, const float *X, float *Y, int32_t m, void *stream);
+extern "C" int sptrsv_launch_mlp_grad(const float *params, const float *X, const float *T, int32_t m, float *grad,
+                                      float *loss, void *workspace, void *stream);
+extern "C" int sptrsv_launch_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step,
+                                      float lr, float beta1, float beta2, float eps, void *stream);
 // FP32 plans: `iterations` refinement steps on x (FP64), all on stream; the
 // steps after convergence (correction <= tol) skip their work on the device.
 extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay,

@@ -19,8 +19,12 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <memory>
 #include <thread>
 
+#include <hip/hip_runtime_api.h>
+
+#include "features.hpp"
 #include "plan.hpp"
 
 namespace sptrsv {
@@ -40,6 +44,12 @@ void validate_policy(const sptrsv_policy &pol) {
     case SPTRSV_POLICY_EXPLICIT:
         if (pol.absorb_len < 0) fail(SPTRSV_ERR_ARG, "policy.absorb_len < 0");
         if (pol.absorb_len > 0 && !pol.absorb) fail(SPTRSV_ERR_ARG, "policy.absorb is NULL");
+        if (pol.max_entries < 0) fail(SPTRSV_ERR_ARG, "policy.max_entries < 0");
+        return;
+    case SPTRSV_POLICY_LEARNED:
+        if (!pol.model) fail(SPTRSV_ERR_ARG, "policy.model is NULL");
+        if (pol.max_depth < 1) fail(SPTRSV_ERR_ARG, "policy.max_depth < 1");
+        if (!(pol.max_fill >= 0.0)) fail(SPTRSV_ERR_ARG, "policy.max_fill must be >= 0");
         if (pol.max_entries < 0) fail(SPTRSV_ERR_ARG, "policy.max_entries < 0");
         return;
     default:
@@ -132,6 +142,57 @@ void parallel_ranges(int64_t count, int threads, F &&f) {
     for (auto &t : pool) t.join();
 }
 
+// Predicted cost (the model's output is the log of a time) of groups of
+// rows, evaluated by the model's forward kernel on the current device.
+class CostModel {
+  public:
+    explicit CostModel(const float *params) : params_(params) {
+        hipError_t e = hipMalloc(&dx_, sizeof(float) * 2 * kFeatures);
+        if (e == hipSuccess) e = hipMalloc(&dy_, sizeof(float) * 2);
+        if (e != hipSuccess) {
+            release();
+            fail(SPTRSV_ERR_HIP, std::string("cost model buffers: ") + hipGetErrorString(e));
+        }
+    }
+    ~CostModel() { release(); }
+    CostModel(const CostModel &) = delete;
+    CostModel &operator=(const CostModel &) = delete;
+
+    // costs of one or two groups
+    void eval(const GroupShape *g, int count, double *cost) {
+        float x[2 * kFeatures], y[2];
+        for (int r = 0; r < count; ++r) group_features(g[r], x + r * kFeatures);
+        hipError_t e = hipMemcpy(dx_, x, sizeof(float) * kFeatures * count, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = (hipError_t)sptrsv_launch_mlp_forward(params_, dx_, dy_, count, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(y, dy_, sizeof(float) * count, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) fail(SPTRSV_ERR_HIP, std::string("cost model: ") + hipGetErrorString(e));
+        for (int r = 0; r < count; ++r) cost[r] = std::exp((double)y[r]);
+    }
+
+  private:
+    void release() {
+        if (dx_) hipFree(dx_);
+        if (dy_) hipFree(dy_);
+        dx_ = dy_ = nullptr;
+    }
+    const float *params_;
+    float *dx_ = nullptr, *dy_ = nullptr;
+};
+
+// Shape of level l left as it is (a stage of its own).
+GroupShape plain_level(const Plan &p, int32_t l) {
+    GroupShape g;
+    for (int32_t q = p.level_ptr[(size_t)l]; q < p.level_ptr[(size_t)l + 1]; ++q) {
+        const int32_t i = p.level_rows[(size_t)q];
+        const int64_t len = p.rp[(size_t)i + 1] - p.rp[(size_t)i];
+        ++g.rows;
+        g.terms += len;
+        g.orig += len;
+        g.maxlen = std::max(g.maxlen, len);
+    }
+    return g;
+}
+
 }  // namespace
 
 void rewrite(Plan &p, const sptrsv_policy &pol) {
@@ -139,7 +200,8 @@ void rewrite(Plan &p, const sptrsv_policy &pol) {
     const int32_t n = p.n, nlev = p.nlev;
     const int64_t nnz = n ? (int64_t)p.rp[(size_t)n] : 0;
     p.policy = pol;
-    p.policy.absorb = nullptr;  // the mask is read during this call only
+    p.policy.absorb = nullptr;  // the mask and the model are read during this call only
+    p.policy.model = nullptr;
     p.stage_of_level.assign((size_t)nlev, 0);
     p.delta_of_level.assign((size_t)nlev, 0);
 
@@ -155,13 +217,25 @@ void rewrite(Plan &p, const sptrsv_policy &pol) {
 
     // ---- stage selection, level by level
     int64_t budget = std::numeric_limits<int64_t>::max();
-    if (pol.kind == SPTRSV_POLICY_THRESHOLD) {
+    if (pol.kind == SPTRSV_POLICY_THRESHOLD || pol.kind == SPTRSV_POLICY_LEARNED) {
         const double lim = pol.max_fill * (double)nnz;
         if (lim < 9.0e18) budget = (int64_t)std::floor(lim);
     }
     int32_t stage = 0, a = 0, depth = 1;
     int64_t added = 0, total = nnz;
     std::vector<std::vector<int32_t>> lvl_x, lvl_b;  // per row of the candidate level
+    // LEARNED: shape and predicted cost of the current stage; a level joins
+    // it when the predicted cost of the merged stage grows by less than the
+    // cost of the level on its own
+    const bool learned = pol.kind == SPTRSV_POLICY_LEARNED;
+    std::unique_ptr<CostModel> model;
+    GroupShape cur;
+    double cur_cost = 0.0;
+    if (learned && nlev > 0) {
+        model.reset(new CostModel(pol.model));
+        cur = plain_level(p, 0);
+        model->eval(&cur, 1, &cur_cost);
+    }
     for (int32_t l = 1; l < nlev; ++l) {
         const int32_t b0 = p.level_ptr[(size_t)l], b1 = p.level_ptr[(size_t)l + 1];
         const int32_t width = b1 - b0;
@@ -170,27 +244,59 @@ void rewrite(Plan &p, const sptrsv_policy &pol) {
             candidate = width <= pol.max_width && depth < pol.max_depth;
         else if (pol.kind == SPTRSV_POLICY_EXPLICIT)
             candidate = l < pol.absorb_len && pol.absorb[l] != 0;
+        else if (learned)
+            candidate = depth < pol.max_depth;
         bool take = false;
-        int64_t delta = 0;
+        int64_t delta = 0, longest = 0;
         if (candidate) {
             lvl_x.resize((size_t)width);
             lvl_b.resize((size_t)width);
-            std::vector<int64_t> part((size_t)threads, 0);
+            std::vector<int64_t> part((size_t)threads, 0), part_max((size_t)threads, 0);
             parallel_ranges(width, threads, [&](int64_t lo, int64_t hi, int w) {
-                int64_t d = 0;
+                int64_t d = 0, mx = 0;
                 for (int64_t q = lo; q < hi; ++q) {
                     const int32_t i = p.level_rows[(size_t)(b0 + q)];
                     row_structure(p, sym, i, a, markers[(size_t)w], lvl_x[(size_t)q], lvl_b[(size_t)q]);
-                    d += (int64_t)lvl_x[(size_t)q].size() + (int64_t)lvl_b[(size_t)q].size() -
-                         (p.rp[(size_t)i + 1] - p.rp[(size_t)i] - 1);
+                    const int64_t len = (int64_t)lvl_x[(size_t)q].size() + (int64_t)lvl_b[(size_t)q].size();
+                    d += len - (p.rp[(size_t)i + 1] - p.rp[(size_t)i] - 1);
+                    mx = std::max(mx, len + 1);
                 }
                 part[(size_t)w] = d;
+                part_max[(size_t)w] = mx;
             });
             for (int64_t d : part) delta += d;
-            if (pol.kind == SPTRSV_POLICY_THRESHOLD)
+            for (int64_t m : part_max) longest = std::max(longest, m);
+            if (pol.kind == SPTRSV_POLICY_THRESHOLD || learned)
                 take = added + delta <= budget && total + delta <= pol.max_entries;
             else
                 take = total + delta <= pol.max_entries;
+        }
+        GroupShape alone;
+        double alone_cost = 0.0;
+        if (learned) {
+            alone = plain_level(p, l);
+            if (take) {
+                GroupShape both[2] = {cur, alone};
+                both[0].rows += alone.rows;
+                both[0].terms += alone.orig + delta;
+                both[0].orig += alone.orig;
+                both[0].maxlen = std::max(cur.maxlen, longest);
+                both[0].span = depth + 1;
+                double c[2];
+                model->eval(both, 2, c);
+                alone_cost = c[1];
+                take = c[0] - cur_cost < alone_cost;
+                if (take) {
+                    cur = both[0];
+                    cur_cost = c[0];
+                }
+            } else {
+                model->eval(&alone, 1, &alone_cost);
+            }
+            if (!take) {
+                cur = alone;
+                cur_cost = alone_cost;
+            }
         }
         if (take) {
             p.stage_of_level[(size_t)l] = stage;

@@ -86,6 +86,8 @@ struct SolveArgs {
     const T *sdiag;
     sptrsv::Workspace *ws;
     const unsigned *skip;  // refinement: the grid returns at once if *skip (NULL: never)
+    unsigned long long *stamps;  // timed solves: completion clock of every item and segment tile
+    long long start_slot;        // stamps[start_slot]: the clock when the grid started
     const T *b;
     T *x;
     long long nitems;
@@ -374,7 +376,7 @@ __device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring)
 // loads are harmless and keep the load count per step fixed).  The compiler
 // barriers keep every stage where it is written: left to itself the
 // scheduler sinks the prefetch loads down to their use.
-template <typename T>
+template <typename T, bool kStamp>
 __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ring) {
     const long long first = d.x, count = d.y, last = first + count - 1;
     SegSlot<T> S[kDepth];
@@ -391,6 +393,7 @@ __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ri
         for (int k = 0; k < kDepth; ++k) {
             const long long t = base + k;
             seg_finish(a, S[k], ring);
+            if (kStamp && lane == 0) a.stamps[a.nitems + first + t] = __builtin_amdgcn_s_memrealtime();
             asm volatile("" ::: "memory");
             __builtin_amdgcn_sched_barrier(0);
             seg_gather(a, S[(k + kDepth / 2) % kDepth]);
@@ -405,11 +408,12 @@ __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ri
 
 // ----------------------------------------------------------------- kernel --
 
-template <typename T>
+template <typename T, bool kStamp>
 __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     __shared__ T ring[kRing];
     const int lane = threadIdx.x;
     long long i = blockIdx.x;
+    if (kStamp && i == 0 && lane == 0) a.stamps[a.start_slot] = __builtin_amdgcn_s_memrealtime();
     if (i >= a.nitems) return;
     if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     int4 d = unpack_item(load_item(a, i, lane));
@@ -419,7 +423,8 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     for (;;) {
         const long long in = i + a.waves, inn = in + a.waves;
         if (is_segment(d)) {
-            run_segment(a, d, lane, ring);
+            run_segment<T, kStamp>(a, d, lane, ring);
+            if (kStamp && lane == 0) a.stamps[i] = __builtin_amdgcn_s_memrealtime();
             if (in >= a.nitems) break;
             d = unpack_item(wnext);
             if (!is_segment(d)) load_tile(a, d, lane, cur);
@@ -472,6 +477,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
             __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + cur.row, Val<T>::bits(xi),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        if (kStamp && lane == 0) a.stamps[i] = __builtin_amdgcn_s_memrealtime();
         if (in >= a.nitems) break;
         cur = nxt;
         d = dnext;
@@ -487,8 +493,8 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
 // updates x += d in FP64 and recomputes r = b - L x in FP64 from the
 // caller's FP64 matrix (one SpMV, a thread per entry of x).  The step's
 // largest correction, relative to max(|x_i|, 1e-3 max|x|), is reduced on the
-// device; once it is <= tol every later kernel of the call returns at once,
-// so the host enqueues a fixed sequence and never waits.
+// device; once the error it implies is <= tol every later kernel of the call
+// returns at once, so the host enqueues a fixed sequence and never waits.
 
 constexpr int kRefBlock = 256;
 constexpr int kRefGrid = 2048;
@@ -561,9 +567,13 @@ __global__ void __launch_bounds__(kRefBlock) refine_update(double *__restrict__ 
     }
 }
 
-// After step t: converged if its correction is <= tol (every block reads the
-// same word and block 0 raises the flag), else r = b - L x in FP64, rounded
-// to FP32 for the next correction, and d32 reset to not ready.
+// After step t: converged if the error left in x is estimated <= tol (every
+// block reads the same words and block 0 raises the flag), else r = b - L x
+// in FP64, rounded to FP32 for the next correction, and d32 reset to not
+// ready.  The correction c_t of step t measures the error x had before it;
+// with linear convergence the error after it is about c_t * rho, the rate
+// rho estimated as c_t / c_{t-1} (capped at 1; from step 2 on, step 0's
+// correction being the whole of x).
 __global__ void __launch_bounds__(kRefBlock) refine_residual(const int4 *__restrict__ sys, int32_t nsys,
                                                              const int32_t *__restrict__ rp,
                                                              const int32_t *__restrict__ col,
@@ -573,23 +583,44 @@ __global__ void __launch_bounds__(kRefBlock) refine_residual(const int4 *__restr
                                                              unsigned *__restrict__ d32, sptrsv::Workspace *ws,
                                                              int32_t n, int t, double tol) {
     if (refine_done(ws)) return;
-    const double ratio = __longlong_as_double((long long)ws->ratio[t]);
-    if (ratio <= tol) {
+    const double c = __longlong_as_double((long long)ws->ratio[t]);
+    const double rho = t >= 2 ? fmin(1.0, c / __longlong_as_double((long long)ws->ratio[t - 1])) : 1.0;
+    if (c * rho <= tol) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             __hip_atomic_store(&ws->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        // system holding device index i: the last with base <= i
+    for (int64_t first = (int64_t)blockIdx.x * kRefBlock; first < n; first += (int64_t)gridDim.x * kRefBlock) {
+        // system holding the block's first index (the last with base <= it);
+        // a thread steps forward from there to its own
         int lo = 0, hi = nsys - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (sys[mid].x <= i) lo = mid; else hi = mid - 1;
+            if (sys[mid].x <= first) lo = mid; else hi = mid - 1;
         }
+        const int32_t i = (int32_t)first + threadIdx.x;
+        if (i >= n) continue;
+        while (lo + 1 < nsys && sys[lo + 1].x <= i) ++lo;
         const int4 S = sys[lo];
         const int32_t rel = i - S.x, row = S.w + rel / S.z, c = rel % S.z;
+        const int32_t e = rp[row + 1];
         double acc = b[i];
-        for (int32_t q = rp[row]; q < rp[row + 1]; ++q) acc = fma(-val[q], x[col[q] + c], acc);
+        // four entries per round, their loads issued together
+        for (int32_t q = rp[row]; q < e; q += 4) {
+            int32_t cc[4];
+            double vv[4], xx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t qq = q + u < e ? q + u : q;
+                cc[u] = col[qq];
+                vv[u] = val[qq];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xx[u] = x[cc[u] + c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u < e) acc = fma(-vv[u], xx[u], acc);
+        }
         r32[i] = (float)acc;
         d32[i] = Val<float>::kNotReady;
     }
@@ -597,8 +628,11 @@ __global__ void __launch_bounds__(kRefBlock) refine_residual(const int4 *__restr
 
 template <typename T>
 SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n, int64_t nitems,
-                        int waves, uint64_t wait_limit, const void *b, void *x, const unsigned *skip) {
+                        int waves, uint64_t wait_limit, const void *b, void *x, const unsigned *skip,
+                        unsigned long long *stamps = nullptr, int64_t start_slot = 0) {
     SolveArgs<T> a;
+    a.stamps = stamps;
+    a.start_slot = start_slot;
     a.items = reinterpret_cast<const int4 *>(dev + lay->tiles);
     a.rows = reinterpret_cast<const int32_t *>(dev + lay->rows);
     a.diag = reinterpret_cast<const T *>(dev + lay->diag);
@@ -619,11 +653,11 @@ SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int
     return a;
 }
 
-template <typename T>
+template <typename T, bool kStamp = false>
 hipError_t launch_tiles(SolveArgs<T> a, int waves, hipStream_t s) {
     void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(solve_tiles<T>), dim3(waves), dim3(64),
-                                      args, 0, s);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(solve_tiles<T, kStamp>), dim3(waves),
+                                      dim3(64), args, 0, s);
 }
 
 int fill_blocks(int32_t n) { return (int)std::min<int64_t>(2048, ((int64_t)n + 255) / 256); }
@@ -638,20 +672,24 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
     if (e != hipSuccess) return (int)e;
     // the FP64 instance holds the larger LDS ring, so it bounds residency
     int b64 = 0, b32 = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, solve_tiles<double>, 64, 0);
+    int bst = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, solve_tiles<double, false>, 64, 0);
     if (e != hipSuccess) return (int)e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, solve_tiles<float>, 64, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, solve_tiles<float, false>, 64, 0);
     if (e != hipSuccess) return (int)e;
-    *max_waves_per_cu = std::min(b64, b32);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bst, solve_tiles<double, true>, 64, 0);
+    if (e != hipSuccess) return (int)e;
+    *max_waves_per_cu = std::min(std::min(b64, b32), bst);
     return 0;
 }
 
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
                                    int64_t nitems, int waves, uint64_t wait_limit, const void *b, void *x,
-                                   void *stream) {
+                                   unsigned long long *stamps, int64_t start_slot, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
     if (lay->value_bytes == 4) {
+        if (stamps) return (int)hipErrorNotSupported;
         hipLaunchKernelGGL(fill_not_ready<float>, dim3(fill_blocks(n)), dim3(256), 0, s,
                            static_cast<unsigned *>(x), n);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
@@ -660,7 +698,9 @@ extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layou
         hipLaunchKernelGGL(fill_not_ready<double>, dim3(fill_blocks(n)), dim3(256), 0, s,
                            static_cast<unsigned long long *>(x), n);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-        e = launch_tiles(solve_args<double>(dev, lay, n, nitems, waves, wait_limit, b, x, nullptr), waves, s);
+        const SolveArgs<double> a =
+            solve_args<double>(dev, lay, n, nitems, waves, wait_limit, b, x, nullptr, stamps, start_slot);
+        e = stamps ? launch_tiles<double, true>(a, waves, s) : launch_tiles<double, false>(a, waves, s);
     }
     return (int)e;
 }

@@ -1,0 +1,318 @@
+"""Learned rewrite policy: training corpus, timing labels, training of the
+cost model with the library's HIP kernels, and the judged plan choice.
+
+The paper picks the levels to rewrite by hand (Sec. IV and V).  Here a
+6-64-64-1 perceptron (FP32, tanh hidden layers) predicts the log of the time
+of one executed level of a schedule from its shape; the LEARNED policy of
+the library absorbs a level into the current stage when the model predicts
+that the merged stage costs less extra time than the level would on its own.
+Labels are measured by the method itself: an instrumented solve stamps the
+GPU clock as every unit of work completes, and the stamps are split into one
+time per executed level (the growth of the completion frontier).  The
+threshold heuristic stays the fallback and the judge: :func:`choose_plan`
+keeps the learned plan only if its measured solve beats the threshold plan.
+
+Every numeric step of training runs in the library's kernels
+(``sptrsv_mlp_grad``, ``sptrsv_mlp_adam``); this module only moves data.
+
+    python -m paper_2103_11445_amd.learn train --out paper_2103_11445_amd/cost_model.npz
+    python -m paper_2103_11445_amd.learn evaluate --model paper_2103_11445_amd/cost_model.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import MLP_INPUTS, MLP_PARAMS, Plan, load, mlp_adam, mlp_grad
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_MODEL = os.path.join(HERE, "cost_model.npz")
+TICKS_PER_US = 100.0          # the GPU real-time clock runs at 100 MHz
+MIN_LEVEL_US = 0.02           # level times are floored here before the log
+INF = 10**9
+
+# the paper's thin-level rule (threshold heuristic): the judge and fallback
+THRESHOLD = ("threshold", {"max_width": 4, "max_depth": 64, "max_fill": 0.25})
+# caps the learned policy works within
+LEARNED_CAPS = {"max_depth": 64, "max_fill": 12.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ corpus --
+
+def corpus_matrix(seed: int, nmin: float = 1e4, nmax: float = 2e5):
+    """One matrix of the training / evaluation corpus: family uniform over
+    {2D stencil, 3D stencil, banded, power-law}, n log-uniform in [nmin,
+    nmax] (stencils use the nearest grid), power-law tail fraction
+    log-uniform in [0.1 %, 5 %]."""
+    import workloads as wl
+    rng = np.random.default_rng(seed)
+    fam = int(rng.integers(0, 4))
+    n = int(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
+    if fam == 0:
+        return wl.stencil2d(max(2, int(round(n ** 0.5))), seed=seed)
+    if fam == 1:
+        return wl.stencil3d(max(2, int(round(n ** (1 / 3)))), seed=seed)
+    if fam == 2:
+        return wl.banded(n, 200, 8, 24, seed=seed)
+    tail = max(1, int(n * np.exp(rng.uniform(np.log(1e-3), np.log(5e-2)))))
+    return wl.powerlaw(n, tail, seed=seed)
+
+
+def label_policies(seed: int):
+    """Schedules a training matrix is measured under: plain, the threshold
+    rule, fixed stage depths, and two random masks (varied stage shapes)."""
+    rng = np.random.default_rng(seed)
+    out = [("none", {}), THRESHOLD]
+    for d in (2, 4, 8, 16):
+        out.append(("threshold", {"max_width": INF, "max_depth": d, "max_fill": 12.0}))
+    for p in (0.5, 0.9):
+        out.append(("explicit", {"absorb_p": p, "seed": int(rng.integers(1 << 30))}))
+    return out
+
+
+def _rewrite(plan: Plan, kind: str, kw: dict, nlev: int):
+    if kind == "explicit":
+        rng = np.random.default_rng(kw["seed"])
+        mask = (rng.random(nlev) < kw["absorb_p"]).astype(np.uint8)
+        # long random stages could multiply the entries: cap them at 13 x nnz(L)
+        return plan.rewrite("explicit", absorb=mask, max_entries=13 * plan.info()["nnz"])
+    return plan.rewrite(kind, **kw)
+
+
+# ------------------------------------------------------------------ labels --
+
+def level_times(stamps: np.ndarray, level: np.ndarray, nlev: int) -> np.ndarray:
+    """Time of every executed level (microseconds) from one instrumented
+    solve: the completion frontier is the latest stamp seen so far, in level
+    order, and a level's time is how far it moves the frontier."""
+    start = int(stamps[-1])
+    ends = np.full(nlev, start, dtype=np.int64)
+    ok = level >= 0
+    np.maximum.at(ends, level[ok], stamps[:-1][ok].astype(np.int64))
+    front = np.maximum.accumulate(np.concatenate([[start], ends]))
+    return np.diff(front).astype(np.float64) / TICKS_PER_US
+
+
+def measure_levels(torch, plan: Plan, b, x, reps: int = 3):
+    """Features and median level times of ``plan`` (uploaded) over ``reps``
+    instrumented solves."""
+    info = plan.info()
+    stamps = torch.empty(info["tiles"] + info["seg_tiles"] + 1, dtype=torch.int64, device=b.device)
+    lv = plan.stamp_levels()
+    times = []
+    plan.solve_stamped(b, x, stamps)  # warm-up
+    for _ in range(reps):
+        plan.solve_stamped(b, x, stamps)
+        times.append(level_times(stamps.cpu().numpy(), lv, info["levels_rw"]))
+    return plan.level_features(), np.median(np.stack(times), axis=0)
+
+
+def collect(torch, seeds, log_every: int = 1):
+    """Training samples (features, log level time) from the corpus matrices
+    drawn from ``seeds``, each measured under :func:`label_policies`."""
+    X, y = [], []
+    for k, seed in enumerate(seeds):
+        s = corpus_matrix(seed)
+        b = torch.from_numpy(s.b).cuda()
+        x = torch.empty_like(b)
+        plan = Plan(s.row_ptr, s.col_idx, s.val)
+        nlev = plan.info()["levels"]
+        rows = 0
+        for kind, kw in label_policies(seed):
+            _rewrite(plan, kind, kw, nlev).upload()
+            f, t = measure_levels(torch, plan, b, x)
+            if plan.check() != 0:
+                raise RuntimeError(f"solve of corpus matrix {seed} timed out")
+            X.append(f)
+            y.append(np.log(np.maximum(t, MIN_LEVEL_US)).astype(np.float32))
+            rows += f.shape[0]
+        plan.close()
+        if k % log_every == 0:
+            log(f"[collect] {k + 1}/{len(seeds)} {s.name}: {rows} level samples")
+    return np.concatenate(X), np.concatenate(y)
+
+
+# ---------------------------------------------------------------- training --
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """Uniform +-1/sqrt(fan-in) weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, (64, MLP_INPUTS)) / np.sqrt(MLP_INPUTS), np.zeros(64),
+             rng.uniform(-1, 1, (64, 64)) / 8.0, np.zeros(64), rng.uniform(-1, 1, 64) / 8.0, np.zeros(1)]
+    p = np.concatenate([q.reshape(-1) for q in parts]).astype(np.float32)
+    assert p.size == MLP_PARAMS
+    return p
+
+
+def train(torch, X: np.ndarray, y: np.ndarray, steps: int = 4000, batch: int = 8192,
+          lr: float = 2e-3, seed: int = 0, log_every: int = 500):
+    """Adam on minibatches, every step in the library's kernels; the
+    learning rate decays to a tenth over the run.  Returns the parameters
+    (numpy float32) and the loss history."""
+    dev = torch.device("cuda")
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+    yd = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(dev)
+    p = torch.from_numpy(init_params(seed)).to(dev)
+    # start from the mean label
+    p[-1] = float(np.mean(y))
+    m1 = torch.zeros_like(p)
+    m2 = torch.zeros_like(p)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    m = X.shape[0]
+    bsz = min(batch, m)
+    grad = loss = ws = None
+    hist = []
+    for k in range(1, steps + 1):
+        idx = torch.randint(0, m, (bsz,), generator=gen).to(dev)
+        xb = Xd.index_select(0, idx).contiguous()
+        tb = yd.index_select(0, idx).contiguous()
+        grad, loss = mlp_grad(p, xb, tb, grad, loss, ws)
+        rate = lr * (0.1 ** (k / steps))
+        mlp_adam(p, grad, m1, m2, k, rate)
+        if k % log_every == 0 or k == steps:
+            hist.append((k, float(loss.item())))
+            log(f"[train] step {k}: minibatch loss {hist[-1][1]:.4f}")
+    return p.cpu().numpy(), hist
+
+
+def save_model(path: str, params: np.ndarray, meta: dict):
+    np.savez(path, params=params.astype(np.float32), meta=np.array(json.dumps(meta)))
+
+
+def load_model(path: str = DEFAULT_MODEL):
+    """(params float32[MLP_PARAMS], meta dict); loads no pickled objects."""
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float32), json.loads(str(z["meta"]))
+
+
+# ------------------------------------------------------------------ choice --
+
+def time_solve(torch, plan: Plan, b, x, reps: int = 7) -> float:
+    """Median time (ms) of one solve, HIP events on the current stream."""
+    s = torch.cuda.current_stream()
+    plan.solve(b, x)
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        plan.solve(b, x)
+        e1.record(s)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return float(np.median(out))
+
+
+def choose_plan(torch, system, model, reps: int = 7):
+    """The judged plan for ``system``: the LEARNED plan if its measured solve
+    beats the threshold plan's, else the threshold plan (also the fallback
+    when there is no model).  Returns (plan, report)."""
+    b = torch.from_numpy(np.ascontiguousarray(system.b)).cuda()
+    x = torch.empty_like(b)
+    heur = Plan(system.row_ptr, system.col_idx, system.val).rewrite(THRESHOLD[0], **THRESHOLD[1]).upload()
+    t_heur = time_solve(torch, heur, b, x, reps)
+    rep = {"threshold_ms": t_heur, "learned_ms": None, "chosen": "threshold"}
+    if model is None:
+        return heur, rep
+    t0 = time.perf_counter()
+    lrn = Plan(system.row_ptr, system.col_idx, system.val).rewrite("learned", model=model, **LEARNED_CAPS)
+    rep["learned_rewrite_s"] = time.perf_counter() - t0
+    lrn.upload()
+    t_lrn = time_solve(torch, lrn, b, x, reps)
+    rep["learned_ms"] = t_lrn
+    rep["levels"] = {"threshold": heur.info()["levels_rw"], "learned": lrn.info()["levels_rw"]}
+    if t_lrn < t_heur:
+        rep["chosen"] = "learned"
+        heur.close()
+        return lrn, rep
+    lrn.close()
+    return heur, rep
+
+
+def evaluate(torch, params: np.ndarray, seeds, reps: int = 7):
+    """Per held-out matrix: plain, threshold and learned solve times and the
+    judged choice; geometric-mean speedups over the threshold plan."""
+    model = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda()
+    rows = []
+    for seed in seeds:
+        s = corpus_matrix(seed)
+        b = torch.from_numpy(s.b).cuda()
+        x = torch.empty_like(b)
+        plain = Plan(s.row_ptr, s.col_idx, s.val).upload()
+        t_plain = time_solve(torch, plain, b, x, reps)
+        plain.close()
+        plan, rep = choose_plan(torch, s, model, reps)
+        plan.close()
+        rep.update({"matrix": s.name, "n": s.n, "plain_ms": t_plain})
+        rep["judged_ms"] = min(rep["threshold_ms"], rep["learned_ms"])
+        rows.append(rep)
+        log(f"[eval] {s.name}: plain {t_plain:.3f} threshold {rep['threshold_ms']:.3f} "
+            f"learned {rep['learned_ms']:.3f} ms -> {rep['chosen']}")
+    g = lambda a: float(np.exp(np.mean(np.log(a))))  # noqa: E731
+    thr = np.array([r["threshold_ms"] for r in rows])
+    summary = {
+        "matrices": len(rows),
+        "geomean_speedup_learned_vs_threshold": g(thr / np.array([r["learned_ms"] for r in rows])),
+        "geomean_speedup_judged_vs_threshold": g(thr / np.array([r["judged_ms"] for r in rows])),
+        "geomean_speedup_judged_vs_plain": g(np.array([r["plain_ms"] for r in rows]) /
+                                             np.array([r["judged_ms"] for r in rows])),
+        "learned_chosen": sum(r["chosen"] == "learned" for r in rows),
+    }
+    return summary, rows
+
+
+# --------------------------------------------------------------------- cli --
+
+TRAIN_SEED, HELDOUT_SEED = 10000, 20000
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--out", default=DEFAULT_MODEL)
+    t.add_argument("--train", type=int, default=240, help="training matrices")
+    t.add_argument("--heldout", type=int, default=40, help="held-out matrices evaluated after training")
+    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--report", default=None, help="JSON file for the evaluation")
+    e = sub.add_parser("evaluate")
+    e.add_argument("--model", default=DEFAULT_MODEL)
+    e.add_argument("--heldout", type=int, default=40)
+    e.add_argument("--report", default=None)
+    args = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))  # the seeded input generators
+    import torch
+    load()
+    if args.cmd == "train":
+        t0 = time.perf_counter()
+        X, y = collect(torch, [TRAIN_SEED + m for m in range(args.train)])
+        t_collect = time.perf_counter() - t0
+        log(f"[collect] {X.shape[0]} samples in {t_collect:.0f} s")
+        params, hist = train(torch, X, y, steps=args.steps)
+        meta = {"train_matrices": args.train, "train_seed": TRAIN_SEED, "samples": int(X.shape[0]),
+                "steps": args.steps, "loss": hist, "label": "ln(level time in microseconds)",
+                "collect_s": t_collect}
+        save_model(args.out, params, meta)
+        log(f"[train] saved {args.out}")
+        params_eval = params
+    else:
+        params_eval, meta = load_model(args.model)
+    if args.heldout:
+        summary, rows = evaluate(torch, params_eval, [HELDOUT_SEED + m for m in range(args.heldout)])
+        log(f"[eval] {summary}")
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump({"summary": summary, "rows": rows, "meta": meta}, f, indent=1)
+        print(json.dumps(summary), flush=True)
+
+
+if __name__ == "__main__":
+    main()

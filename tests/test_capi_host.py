@@ -274,13 +274,14 @@ def test_batch_plan_is_the_union_plan(sp):
     rows, cols, vals, base = [], [], [], 0
     rp = [0]
     for s, k in zip(corp, ks):
-        for c in range(k):
-            for i in range(s.n):
+        # copy c of row i is union row base + i*k + c
+        for i in range(s.n):
+            for c in range(k):
                 seg = slice(s.row_ptr[i], s.row_ptr[i + 1])
-                cols.append(s.col_idx[seg] + base)
+                cols.append(base + s.col_idx[seg] * k + c)
                 vals.append(s.val[seg])
                 rp.append(rp[-1] + (s.row_ptr[i + 1] - s.row_ptr[i]))
-            base += s.n
+        base += s.n * k
     rp = np.array(rp, np.int32)
     ci = np.concatenate(cols).astype(np.int32)
     v = np.concatenate(vals)
@@ -351,3 +352,81 @@ def test_fp32_errors_without_gpu(sp):
     assert sp.STATUS[lib.sptrsv_refine_stats(plan._h, None, ctypes.byref(it), ctypes.byref(corr))] == "ERR_STATE"
     plan.set_precision(32)
     assert sp.STATUS[lib.sptrsv_solve(plan._h, None, None, None)] == "ERR_STATE"
+
+
+def test_fp32_batch_plan_packs(sp):
+    """FP32 packing of batched plans (systems of different sizes and
+    right-hand-side counts) and of upper plans: the residual matrix the
+    packer rebuilds has exactly the callers' entries (the packer checks its
+    counts and fails with ERR_STATE otherwise)."""
+    corp = wl.batch_corpus(6, nmin=200, nmax=20000, ks=(1, 3, 8), seed=29)
+    ks = [1 if s.b.ndim == 1 else s.b.shape[1] for s in corp]
+    plan = sp.Plan.batch([(s.row_ptr, s.col_idx, s.val) for s in corp], ks)
+    b64 = plan.info()["device_bytes"]
+    plan.set_precision(32).rewrite("threshold", max_width=10**9, max_depth=8, max_fill=12.0)
+    assert plan.info()["precision"] == 32
+    nnz = sum(s.nnz for s in corp)
+    rows = sum(s.n * k for s, k in zip(corp, ks))
+    assert plan.info()["device_bytes"] >= 12 * nnz + 8 * rows
+    U = wl.transpose(wl.powerlaw(5000, 300, seed=3))
+    sp.Plan(U.row_ptr, U.col_idx, U.val, upper=True).set_precision(32)
+    assert b64 > 0
+
+
+# -------------------------------------------- learned-policy host pieces --
+
+def _group_features(rows, terms, orig, maxlen, span):
+    """The documented feature formula, written out independently."""
+    return np.array([np.log2(1 + rows) / 16, np.log2(1 + terms) / 24,
+                     min(16.0, max(terms - orig, 0) / max(orig, 1)) / 4, np.log2(1 + maxlen) / 8,
+                     min(256.0, terms / max(rows, 1)) / 16, np.log2(max(span, 1)) / 8], dtype=np.float32)
+
+
+def test_level_features_plain_and_rewritten(sp):
+    """Features of the executed levels, recomputed here from the exported
+    rewritten system and the levels of L."""
+    s = wl.powerlaw(3000, 200, seed=11)
+    for kind, kw in [("none", {}), ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 10.0})]:
+        plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite(kind, **kw)
+        f = plan.level_features()
+        (lp_ptr, _, _), (m_ptr, _, _) = plan.export()
+        lev0 = plan.levels(0)
+        ptr, rows = plan.schedule()
+        assert f.shape == (plan.info()["levels_rw"], 6)
+        for l in range(0, f.shape[0], max(1, f.shape[0] // 25)):
+            r = rows[ptr[l]:ptr[l + 1]]
+            lens = (lp_ptr[r + 1] - lp_ptr[r]) + (m_ptr[r + 1] - m_ptr[r])
+            orig = int(np.sum(s.row_ptr[r + 1] - s.row_ptr[r]))
+            want = _group_features(r.size, int(lens.sum()), orig, int(lens.max()),
+                                   int(lev0[r].max() - lev0[r].min() + 1))
+            assert np.allclose(f[l], want, rtol=1e-6, atol=1e-7), (kind, l)
+
+
+INF = 10**9
+
+
+def test_stamp_levels_cover_every_level(sp):
+    """Every executed level is finished by at least one stamp unit, and the
+    map only names existing levels (or -1)."""
+    for make in (lambda: wl.bidiagonal(3000, seed=1), lambda: wl.stencil3d(16, seed=2),
+                 lambda: wl.powerlaw(20000, 2000, seed=3)):
+        s = make()
+        plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+        lv = plan.stamp_levels()
+        info = plan.info()
+        assert lv.size == info["tiles"] + info["seg_tiles"]
+        assert lv.min() >= -1 and lv.max() < info["levels_rw"]
+        assert np.array_equal(np.unique(lv[lv >= 0]), np.arange(info["levels_rw"]))
+
+
+def test_learned_policy_needs_a_model(sp):
+    s = wl.stencil2d(8, seed=0)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    with pytest.raises(sp.SptrsvError) as e:
+        plan.rewrite("learned", max_depth=8)
+    assert e.value.status == "ERR_ARG"
+    lib = sp.load()
+    assert sp.STATUS[lib.sptrsv_mlp_grad_workspace(0, None)] == "ERR_ARG"
+    assert sp.STATUS[lib.sptrsv_mlp_forward(None, None, None, 0, None)] == "OK"   # nothing to do
+    assert sp.STATUS[lib.sptrsv_mlp_forward(None, None, None, 4, None)] == "ERR_ARG"
+    assert sp.STATUS[lib.sptrsv_mlp_adam(None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, None)] == "ERR_ARG"
