@@ -48,7 +48,7 @@ def log(*a):
 
 # ------------------------------------------------------------------ corpus --
 
-def corpus_matrix(seed: int, nmin: float = 1e4, nmax: float = 2e5):
+def corpus_matrix(seed: int, nmin: float = 1e4, nmax: float = 1e6):
     """One matrix of the training / evaluation corpus: family uniform over
     {2D stencil, 3D stencil, banded, power-law}, n log-uniform in [nmin,
     nmax] (stencils use the nearest grid), power-law tail fraction
@@ -116,11 +116,19 @@ def measure_levels(torch, plan: Plan, b, x, reps: int = 3):
     return plan.level_features(), np.median(np.stack(times), axis=0)
 
 
-def collect(torch, seeds, log_every: int = 1):
+def collect(torch, seeds, log_every: int = 1, budget_s: float = float("inf")):
     """Training samples (features, log level time) from the corpus matrices
-    drawn from ``seeds``, each measured under :func:`label_policies`."""
+    drawn from ``seeds``, each measured under :func:`label_policies`; stops
+    early once ``budget_s`` seconds have passed.  Returns (X, y, matrices
+    used)."""
     X, y = [], []
+    t0 = time.perf_counter()
+    used = 0
     for k, seed in enumerate(seeds):
+        if time.perf_counter() - t0 > budget_s:
+            log(f"[collect] time budget reached after {used} matrices")
+            break
+        used += 1
         s = corpus_matrix(seed)
         b = torch.from_numpy(s.b).cuda()
         x = torch.empty_like(b)
@@ -138,7 +146,7 @@ def collect(torch, seeds, log_every: int = 1):
         plan.close()
         if k % log_every == 0:
             log(f"[collect] {k + 1}/{len(seeds)} {s.name}: {rows} level samples")
-    return np.concatenate(X), np.concatenate(y)
+    return np.concatenate(X), np.concatenate(y), used
 
 
 # ---------------------------------------------------------------- training --
@@ -237,13 +245,19 @@ def choose_plan(torch, system, model, reps: int = 7):
     return heur, rep
 
 
-def evaluate(torch, params: np.ndarray, seeds, reps: int = 7):
+def evaluate(torch, params: np.ndarray, seeds, reps: int = 7, nmax: float = 1e6,
+             budget_s: float = float("inf")):
     """Per held-out matrix: plain, threshold and learned solve times and the
-    judged choice; geometric-mean speedups over the threshold plan."""
+    judged choice; geometric-mean speedups over the threshold plan.  Stops
+    early once ``budget_s`` seconds have passed."""
     model = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda()
     rows = []
+    t0 = time.perf_counter()
     for seed in seeds:
-        s = corpus_matrix(seed)
+        if time.perf_counter() - t0 > budget_s:
+            log(f"[eval] time budget reached after {len(rows)} matrices")
+            break
+        s = corpus_matrix(seed, nmax=nmax)
         b = torch.from_numpy(s.b).cuda()
         x = torch.empty_like(b)
         plain = Plan(s.row_ptr, s.col_idx, s.val).upload()
@@ -282,10 +296,12 @@ def main(argv=None):
     t.add_argument("--train", type=int, default=240, help="training matrices")
     t.add_argument("--heldout", type=int, default=40, help="held-out matrices evaluated after training")
     t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--budget", type=float, default=float("inf"), help="seconds for collecting labels")
     t.add_argument("--report", default=None, help="JSON file for the evaluation")
     e = sub.add_parser("evaluate")
     e.add_argument("--model", default=DEFAULT_MODEL)
     e.add_argument("--heldout", type=int, default=40)
+    e.add_argument("--budget", type=float, default=float("inf"), help="seconds for the evaluation")
     e.add_argument("--report", default=None)
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))  # the seeded input generators
@@ -293,11 +309,12 @@ def main(argv=None):
     load()
     if args.cmd == "train":
         t0 = time.perf_counter()
-        X, y = collect(torch, [TRAIN_SEED + m for m in range(args.train)])
+        X, y, used = collect(torch, [TRAIN_SEED + m for m in range(args.train)], budget_s=args.budget)
         t_collect = time.perf_counter() - t0
-        log(f"[collect] {X.shape[0]} samples in {t_collect:.0f} s")
+        log(f"[collect] {X.shape[0]} samples from {used} matrices in {t_collect:.0f} s")
         params, hist = train(torch, X, y, steps=args.steps)
-        meta = {"train_matrices": args.train, "train_seed": TRAIN_SEED, "samples": int(X.shape[0]),
+        meta = {"train_matrices": used, "train_seed": TRAIN_SEED, "samples": int(X.shape[0]),
+                "n_range": [1e4, 1e6],
                 "steps": args.steps, "loss": hist, "label": "ln(level time in microseconds)",
                 "collect_s": t_collect}
         save_model(args.out, params, meta)
@@ -306,7 +323,8 @@ def main(argv=None):
     else:
         params_eval, meta = load_model(args.model)
     if args.heldout:
-        summary, rows = evaluate(torch, params_eval, [HELDOUT_SEED + m for m in range(args.heldout)])
+        summary, rows = evaluate(torch, params_eval, [HELDOUT_SEED + m for m in range(args.heldout)],
+                                 budget_s=args.budget if args.cmd == "evaluate" else float("inf"))
         log(f"[eval] {summary}")
         if args.report:
             with open(args.report, "w") as f:

@@ -200,7 +200,7 @@ def test_learned_gain_on_heldout(torch, sp, model):
     from paper_2103_11445_amd.learn import HELDOUT_SEED, evaluate
     params = model[0].cpu().numpy()
     seeds = [HELDOUT_SEED + 100 + m for m in range(8)]
-    summary, rows = evaluate(torch, params, seeds, reps=5)
+    summary, rows = evaluate(torch, params, seeds, reps=5, nmax=2e5)
     print(summary, flush=True)
     for r in rows:
         print(r["matrix"], r["threshold_ms"], r["learned_ms"], r["chosen"], flush=True)
