@@ -42,22 +42,63 @@ INF = 10**9
 # Candidate policies of the threshold rule.  "paper" is the thin-level rule
 # with its default parameters; "depthD" absorbs every level into stages of D
 # levels (every level is thin for a GPU that runs thousands of rows at once),
-# with at most 12 x nnz(L) added entries.
+# with at most 12 x nnz(L) added entries.  "learned" (added at run time when
+# the trained cost model is present) lets the cost model pick the stages.
 CANDIDATES = {
     "plain": ("none", {}),
     "paper": ("threshold", {"max_width": 4, "max_depth": 64, "max_fill": 0.25}),
     "depth2": ("threshold", {"max_width": INF, "max_depth": 2, "max_fill": 12.0}),
     "depth4": ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 12.0}),
-    "depth8": ("threshold", {"max_width": INF, "max_depth": 8, "max_fill": 12.0}),
     "depth16": ("threshold", {"max_width": INF, "max_depth": 16, "max_fill": 12.0}),
+    # deep stages trade HBM bytes (up to ~40 x nnz(L)) for synchronisation
+    # points: affordable with 288 GB of HBM
+    "depth64": ("threshold", {"max_width": INF, "max_depth": 64, "max_fill": 40.0}),
+    "depth128": ("threshold", {"max_width": INF, "max_depth": 128, "max_fill": 48.0}),
+    "depth256": ("threshold", {"max_width": INF, "max_depth": 256, "max_fill": 72.0}),
 }
 # Result of the tuning leg on MI355X (used by --no-tune, e.g. under a profiler).
-TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth16", "powerlaw_4m": "paper",
+TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth256", "powerlaw_4m": "paper",
          "stencil2d_100": "paper"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+PROFILE = os.path.join(ROOT, "profiles", "solve_tiles_large.md")
+KERNEL_SOURCES = ["solve.hip", "plan.hpp", "pack.cpp", "rewrite.cpp", "analyse.cpp"]
+
+
+def kernel_sources_hash() -> str:
+    """Hash of what fixes the solve kernel's memory traffic on the large
+    workload: the kernel and device-image sources and the tuned policies."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_11445_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    h.update(json.dumps({n: CANDIDATES[TUNED[n]] for n in LARGE}, sort_keys=True).encode())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per step and per matrix of the solve kernel from the
+    committed rocprofv3 counter summary, if it was taken of the current
+    kernel and plans (else None)."""
+    try:
+        with open(PROFILE) as f:
+            text = f.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for line in text:
+        if ":" in line and (line.startswith("kernel_sources_sha256") or line.startswith("traffic_bytes")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    return {"step": float(kv["traffic_bytes_per_step"]),
+            **{n: float(kv[f"traffic_bytes {n}"]) for n in LARGE if f"traffic_bytes {n}" in kv}}
 
 
 def main():
@@ -102,6 +143,11 @@ def main():
     if args.workload == "precision":
         return bench_precision(args, torch, sp, workloads, stream)
     names = LARGE if args.workload == "large" else SMALL
+    # the learned policy joins the candidates when the trained cost model is there
+    from paper_2103_11445_amd.learn import DEFAULT_MODEL, LEARNED_CAPS, load_model
+    if os.path.exists(DEFAULT_MODEL):
+        params, _ = load_model(DEFAULT_MODEL)
+        CANDIDATES["learned"] = ("learned", {**LEARNED_CAPS, "model": torch.from_numpy(params).to(dev)})
 
     systems, host = {}, {}
     for name in names:
@@ -258,6 +304,14 @@ def main():
     # every solve), against the 8 TB/s HBM peak
     kern_ms = sum(per.values())
     achieved = sum(plans[n].info()["bytes_rw"] for n in names) / (kern_ms * 1e-3) / 1e9
+    # measured HBM bytes (rocprofv3 counters, calibrated) of the same kernel,
+    # plans and workload; only valid for the tuned policies it was taken with
+    traffic = None
+    if args.workload == "large" and all(chosen[n] == TUNED[n] for n in names):
+        traffic = profiled_traffic()
+    if traffic is not None:
+        for n in names:
+            matrices[n]["traffic_bytes"] = traffic.get(n)
     out = {
         "metric": "SpTRSV solves/s + achieved HBM GB/s vs plain level-set, rel err <=1e-10",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -267,7 +321,9 @@ def main():
                                 if args.workload == "large" else "stencil2d_100, FP64 CSR int32, 1 RHS"),
                    "solves_per_step": nsolve},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     # per launch like "achieved": the step's three launches averaged
+                     "traffic": None if traffic is None else traffic["step"] / len(names)},
         "cpu_baseline": cpu,
         "parity_ok": parity,
         "plain_levelset": None if plain_res is None else {

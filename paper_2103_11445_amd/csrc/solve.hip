@@ -457,18 +457,30 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         T acc = T(0);
 #pragma unroll
         for (int c = 0; c < kRegChunks; ++c) acc = fma(tile_val(cur, c, lane), term_value<T>(col[c], g[c]), acc);
-        // 4. rows longer than the register chunks: stream the rest
-        if (cur.d.z > kRegChunks) {
-            if (tile_active(cur.d, lane)) {
-                const size_t base = (size_t)cur.d.x * 64 + lane;
-                for (int c = kRegChunks; c < cur.d.z; ++c) {
-                    const int32_t k = a.tcol[base + (size_t)c * 64];
-                    const T v = a.tval[base + (size_t)c * 64];
-                    typename Val<T>::Bits gv = load_cached(gather_addr(a, k));
-                    if (pending(a, k, gv)) gv = wait_slow(a.x, k, a.ws, a.wait_limit);
-                    acc = fma(v, term_value<T>(k, gv), acc);
-                }
+        // 4. rows longer than the register chunks: the rest, kRegChunks
+        //    chunks at a time, each group's loads and gathers issued together
+        //    (the chunk count is uniform over the wave; pads and inactive
+        //    lanes read their own pad slot and count as kPad)
+        for (int c0 = kRegChunks; c0 < cur.d.z; c0 += kRegChunks) {
+            const bool act = tile_active(cur.d, lane);
+            const size_t base = (size_t)cur.d.x * 64 + lane;
+            int32_t kc[kRegChunks];
+            T vc[kRegChunks];
+            typename Val<T>::Bits gc[kRegChunks];
+#pragma unroll
+            for (int u = 0; u < kRegChunks; ++u) {
+                const size_t idx = base + (size_t)(c0 + u < cur.d.z ? c0 + u : c0) * 64;
+                kc[u] = a.tcol[idx];
+                vc[u] = a.tval[idx];
             }
+#pragma unroll
+            for (int u = 0; u < kRegChunks; ++u) {
+                if (!act || c0 + u >= cur.d.z) kc[u] = kPad;
+                gc[u] = load_cached(gather_addr(a, kc[u]));
+            }
+            resolve_pending<kRegChunks, true>(a, kc, gc);
+#pragma unroll
+            for (int u = 0; u < kRegChunks; ++u) acc = fma(vc[u], term_value<T>(kc[u], gc[u]), acc);
         }
         // 5. row sums across the row's lanes, then x_i
         acc = group_sum(acc, cur.d.w & 0xff);
