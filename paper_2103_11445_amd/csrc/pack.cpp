@@ -1,13 +1,20 @@
 // pack.cpp -- device image of a plan: the executed schedule (level sets of
-// L') as a list of work items in level order.
+// L') as a list of work items in level order, and the right-hand-side
+// combination b' = b + M b as a separate set of tiles.
+//
+// Right-hand side.  The b-terms of the rewritten rows depend on nothing the
+// solve computes, so they are not part of the schedule: a fully parallel
+// pass over "M tiles" (rows binned by their count of b-terms, the same tile
+// shape as below) computes b'_i = b_i + sum_j M_ij b_j for every row (and
+// resets x) before the dependent solve starts.  The solve tiles hold x-terms
+// only and read b'_i.
 //
 // Wide items.  Within a level, rows are binned by term count (b-terms +
 // x-terms): a row of `len` terms gets g lanes, the smallest power of two with
 // len <= kTermsPerLane * g (capped at 64).  A tile holds 64/g rows of one bin
 // of one level; its terms occupy `nchunks` chunks of 64 slots, the t-th term
-// of the tile's r-th row at chunk t / g, lane r * g + t % g.  Each row lists
-// its b-terms (column ~j, coefficient M_ij) before its x-terms (column k,
-// coefficient -L'_ik); unused slots hold INT32_MIN.
+// of the tile's r-th row at chunk t / g, lane r * g + t % g.  A term is an
+// x-term (column k, coefficient -L'_ik); unused slots hold INT32_MIN.
 //
 // Segments.  A level is narrow when its rows fit in at most kNarrowTiles
 // tiles of kSegChunks chunks (g = 64 / rows-per-tile, as many lanes per row
@@ -57,9 +64,7 @@ void pack(Plan &p) {
     if ((int64_t)n + kRing > INT32_MAX)
         throw Error{SPTRSV_ERR_OVERFLOW, "n too large for the device encoding"};
     std::vector<int64_t> len((size_t)n);
-    for (int32_t i = 0; i < n; ++i)
-        len[(size_t)i] = (p.lp_ptr[(size_t)i + 1] - p.lp_ptr[(size_t)i] - 1) +
-                         (p.m_ptr[(size_t)i + 1] - p.m_ptr[(size_t)i]);
+    for (int32_t i = 0; i < n; ++i) len[(size_t)i] = p.lp_ptr[(size_t)i + 1] - p.lp_ptr[(size_t)i] - 1;
 
     // ---- classify levels: narrow levels and their segment tile shape
     const int32_t L = p.nlev_rw;
@@ -162,6 +167,41 @@ void pack(Plan &p) {
             if (it.kind == 1) seg_first[(size_t)++sid] = stiles[(size_t)it.a].row_off;
     }
 
+    // ---- M tiles: every row once, binned by its b-term count, in the order
+    // of the caller's indices within a bin (so the pass reads b and writes b'
+    // and x in runs of consecutive entries)
+    std::vector<int32_t> mslot_row((size_t)n);
+    std::vector<Tile> mtiles;
+    int64_t mchunks = 0;
+    {
+        int32_t cnt[kBins] = {0};
+        auto mlen = [&](int32_t i) { return p.m_ptr[(size_t)i + 1] - p.m_ptr[(size_t)i]; };
+        auto row_at = [&](int32_t d) { return p.upper ? n - 1 - d : d; };  // plan row of caller index d
+        for (int32_t i = 0; i < n; ++i) ++cnt[bin_of(mlen(i))];
+        int32_t start[kBins], cur[kBins], acc = 0;
+        for (int g = 0; g < kBins; ++g) {
+            start[g] = cur[g] = acc;
+            acc += cnt[g];
+        }
+        for (int32_t d = 0; d < n; ++d) {
+            const int32_t r = row_at(d);
+            mslot_row[(size_t)cur[bin_of(mlen(r))]++] = r;
+        }
+        for (int g = 0; g < kBins; ++g) {
+            const int32_t per = 64 >> g;
+            for (int32_t s = start[g]; s < start[g] + cnt[g]; s += per) {
+                const int32_t nr = std::min(per, start[g] + cnt[g] - s);
+                int64_t mx = 0;
+                for (int32_t r = 0; r < nr; ++r) mx = std::max(mx, mlen(mslot_row[(size_t)(s + r)]));
+                const int64_t nch = (mx + (1 << g) - 1) >> g;
+                mtiles.push_back({mchunks, s, (int32_t)nch, nr, g});
+                mchunks += nch;
+            }
+        }
+    }
+    if (mchunks > INT32_MAX || (int64_t)mtiles.size() > INT32_MAX)
+        throw Error{SPTRSV_ERR_OVERFLOW, "device image needs more than INT32_MAX chunks"};
+
     // ---- layout
     const int64_t nst = (int64_t)stiles.size();
     const bool f32 = p.precision == 32;
@@ -190,6 +230,17 @@ void pack(Plan &p) {
     off = align256(off + (size_t)nst * 64 * 8);
     Ly.sdiag = off;
     off = align256(off + (size_t)nst * 64 * vb);
+    Ly.mtiles = off;
+    off = align256(off + mtiles.size() * 16);
+    Ly.mrow = off;
+    off = align256(off + (size_t)n * 4);
+    Ly.mcol = off;
+    off = align256(off + (size_t)mchunks * 64 * 4);
+    Ly.mval = off;
+    off = align256(off + (size_t)mchunks * 64 * vb);
+    Ly.bp = off;
+    off = align256(off + (size_t)n * vb);
+    Ly.nmtiles = (int64_t)mtiles.size();
     if (f32) {
         Ly.nsys = (int32_t)p.sys_n.size();
         for (size_t j = 0; j < p.sys_n.size(); ++j) {
@@ -240,10 +291,8 @@ void pack(Plan &p) {
         putv(Ly.diag, s, p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1]);
     }
 
-    // terms of row i for a tile with 2^lg lanes per row, written through put(col, val)
+    // x-terms of row i for a tile with 2^lg lanes per row, written through put(col, val)
     auto row_terms = [&](int32_t i, int32_t seg, int32_t first_slot_of_tile, auto &&put) {
-        for (int64_t q = p.m_ptr[(size_t)i]; q < p.m_ptr[(size_t)i + 1]; ++q)
-            put(~orig(p.m_col[(size_t)q]), p.m_val[(size_t)q]);
         for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q) {
             const int32_t k = p.lp_col[(size_t)q];
             int32_t col = orig(k);
@@ -303,6 +352,31 @@ void pack(Plan &p) {
                 putv(Ly.tval, idx, v);
                 ++t_;
             });
+        }
+    }
+    {
+        // M tiles: b-terms (device index of b_j, coefficient M_ij)
+        int32_t *mdesc = reinterpret_cast<int32_t *>(img + Ly.mtiles);
+        int32_t *mrow = reinterpret_cast<int32_t *>(img + Ly.mrow);
+        int32_t *mcol = reinterpret_cast<int32_t *>(img + Ly.mcol);
+        std::fill(mcol, mcol + mchunks * 64, kPad);
+        for (int32_t s = 0; s < n; ++s) mrow[s] = orig(mslot_row[(size_t)s]);
+        for (size_t t = 0; t < mtiles.size(); ++t) {
+            const Tile &T = mtiles[t];
+            mdesc[4 * t + 0] = (int32_t)T.chunk_off;
+            mdesc[4 * t + 1] = T.row_off;
+            mdesc[4 * t + 2] = T.nch;
+            mdesc[4 * t + 3] = (T.nrows << 8) | T.lg;
+            const int32_t g = 1 << T.lg;
+            for (int32_t r = 0; r < T.nrows; ++r) {
+                const int32_t i = mslot_row[(size_t)(T.row_off + r)];
+                int64_t t_ = 0;
+                for (int64_t q = p.m_ptr[(size_t)i]; q < p.m_ptr[(size_t)i + 1]; ++q, ++t_) {
+                    const int64_t idx = (T.chunk_off + (t_ >> T.lg)) * 64 + r * g + (t_ & (g - 1));
+                    mcol[idx] = orig(p.m_col[(size_t)q]);
+                    putv(Ly.mval, idx, p.m_val[(size_t)q]);
+                }
+            }
         }
     }
     if (f32) {

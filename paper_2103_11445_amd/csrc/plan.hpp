@@ -43,6 +43,13 @@ struct Layout {
     size_t srow = 0;       // int32[nseg_tiles][64][2]: row finished by the lane (-1 if none),
                            //   log2 lanes per row | ring index << 8
     size_t sdiag = 0;      // double[nseg_tiles][64] its diagonal
+    // right-hand side b' = b + M b, computed by a parallel pass before the solve
+    size_t mtiles = 0;     // int4[nmtiles]: {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
+    size_t mrow = 0;       // int32[n]  device row of each M-tile slot
+    size_t mcol = 0;       // int32[64*mchunks] device index of b_j (INT32_MIN pad)
+    size_t mval = 0;       // double[64*mchunks] M_ij
+    size_t bp = 0;         // double[n] b' (device indices), written by the pass
+    int64_t nmtiles = 0;
     // FP32 plans only: what iterative refinement needs next to the FP32
     // schedule -- the caller's matrices in FP64 for the residual, and two
     // FP32 vectors (residual, correction) indexed like b and x

@@ -24,7 +24,9 @@
 //     memory, and the wave runs a software pipeline: term loads kDepth tiles
 //     ahead, b / external-x gathers kDepth/2 tiles ahead, so the critical
 //     path waits only on LDS and on loads issued several tiles before.
-//   * b-terms (the rewritten right-hand side) never wait.
+//   * The rewritten right-hand side b' = b + M b depends on nothing the
+//     solve computes: a fully parallel pass (prepare) computes it, and resets
+//     x, before the dependent solve, whose terms are then x-terms only.
 //   * The same kernels run in FP64 or, for plans stored in FP32, in FP32
 //     (values, arithmetic and x; the readiness pattern is then an FP32
 //     signalling NaN); iterative refinement adds an FP64 residual and an
@@ -88,7 +90,7 @@ struct SolveArgs {
     const unsigned *skip;  // refinement: the grid returns at once if *skip (NULL: never)
     unsigned long long *stamps;  // timed solves: completion clock of every item and segment tile
     long long start_slot;        // stamps[start_slot]: the clock when the grid started
-    const T *b;
+    const T *b;  // b' = b + M b (written by prepare)
     T *x;
     long long nitems;
     long long waves;
@@ -98,11 +100,7 @@ struct SolveArgs {
 
 __device__ inline bool is_segment(const int4 d) { return d.w < 0; }
 
-template <typename T>
-__global__ void fill_not_ready(typename Val<T>::Bits *__restrict__ x, int32_t n) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        x[i] = Val<T>::kNotReady;
-}
+
 
 template <typename T>
 __device__ inline typename Val<T>::Bits load_agent(const T *p) {
@@ -144,14 +142,11 @@ __device__ __noinline__ typename Val<T>::Bits wait_slow(const T *x, int32_t k, s
     }
 }
 
-// Address a term gathers from: x_k for x-terms (0 <= k < n), b_j for b-terms
-// (k = ~j), the dummy b_0 otherwise.
+// Address a term gathers from: x_k for x-terms (0 <= k < n), the dummy b'_0
+// for pads and LDS-ring terms (k >= n, read from the ring instead).
 template <typename T>
 __device__ inline const T *gather_addr(const SolveArgs<T> &a, int32_t k) {
-    const T *p = a.b;
-    if (k >= 0 && k < a.n) p = a.x + k;
-    if (k < 0 && k != kPad) p = a.b + ~k;
-    return p;
+    return k >= 0 && k < a.n ? a.x + k : a.b;
 }
 
 template <typename T>
@@ -247,6 +242,63 @@ __device__ inline int load_item(const SolveArgs<T> &a, long long i, int lane) {
 __device__ inline int4 unpack_item(int w) {
     return make_int4(__builtin_amdgcn_readlane(w, 0), __builtin_amdgcn_readlane(w, 1),
                      __builtin_amdgcn_readlane(w, 2), __builtin_amdgcn_readlane(w, 3));
+}
+
+// ---------------------------------------------------------------- prepare --
+
+template <typename T>
+struct PrepArgs {
+    const int4 *tiles;       // M tiles
+    const int32_t *rows;     // device row of each M-tile slot
+    const int32_t *col;      // b-term columns (device index of b_j), kPad for pads
+    const T *val;            // M_ij
+    const T *b;
+    T *bp;                   // out: b'
+    typename Val<T>::Bits *x;  // out: the not-ready pattern
+    long long ntiles;
+    const unsigned *skip;    // refinement: return at once if *skip
+};
+
+// b'_i = b_i + sum_j M_ij b_j and x_i = not ready, for every row: one wave per
+// M tile (grid-stride), its chunks in groups of four with every load issued
+// before the first use.  Nothing here waits on another wave.
+template <typename T>
+__global__ void __launch_bounds__(256) prepare(PrepArgs<T> a) {
+    if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int lane = threadIdx.x & 63;
+    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long t = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < a.ntiles; t += nw) {
+        const int4 dv = a.tiles[t];
+        const int4 d = make_int4(__builtin_amdgcn_readfirstlane(dv.x), __builtin_amdgcn_readfirstlane(dv.y),
+                                 __builtin_amdgcn_readfirstlane(dv.z), __builtin_amdgcn_readfirstlane(dv.w));
+        const int lg = d.w & 0xff, nrows = d.w >> 8;
+        const bool active = (lane >> lg) < nrows;
+        const size_t base = (size_t)d.x * 64 + lane;
+        T acc = T(0);
+        for (int c0 = 0; c0 < d.z; c0 += 4) {
+            int32_t k[4];
+            T v[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t idx = base + (size_t)(c0 + u < d.z ? c0 + u : c0) * 64;
+                k[u] = a.col[idx];
+                v[u] = a.val[idx];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (!active || c0 + u >= d.z) k[u] = kPad;
+                bv[u] = a.b[k[u] == kPad ? 0 : k[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = fma(v[u], k[u] == kPad ? T(0) : bv[u], acc);
+        }
+        acc = group_sum(acc, lg);
+        if (active && (lane & ((1 << lg) - 1)) == 0) {
+            const int32_t row = a.rows[d.y + (lane >> lg)];
+            a.bp[row] = a.b[row] + acc;
+            a.x[row] = Val<T>::kNotReady;
+        }
+    }
 }
 
 // ----------------------------------------------------------- wide tiles --
@@ -532,10 +584,10 @@ __device__ inline bool refine_done(const sptrsv::Workspace *ws) {
     return __hip_atomic_load(&ws->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
 }
 
-// x = 0, r32 = b rounded, d32 = not ready; clears the refinement words.
+// x = 0, r32 = b rounded; clears the refinement words.
 __global__ void __launch_bounds__(kRefBlock) refine_init(const double *__restrict__ b, double *__restrict__ x,
-                                                         float *__restrict__ r32, unsigned *__restrict__ d32,
-                                                         sptrsv::Workspace *ws, int32_t n) {
+                                                         float *__restrict__ r32, sptrsv::Workspace *ws,
+                                                         int32_t n) {
     const int32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid == 0) {
         ws->done = 0u;
@@ -548,7 +600,6 @@ __global__ void __launch_bounds__(kRefBlock) refine_init(const double *__restric
     for (int32_t i = tid; i < n; i += gridDim.x * blockDim.x) {
         x[i] = 0.0;
         r32[i] = (float)b[i];
-        d32[i] = Val<float>::kNotReady;
     }
 }
 
@@ -581,8 +632,7 @@ __global__ void __launch_bounds__(kRefBlock) refine_update(double *__restrict__ 
 
 // After step t: converged if the error left in x is estimated <= tol (every
 // block reads the same words and block 0 raises the flag), else r = b - L x
-// in FP64, rounded to FP32 for the next correction, and d32 reset to not
-// ready.  The correction c_t of step t measures the error x had before it;
+// in FP64, rounded to FP32 for the next correction.  The correction c_t of step t measures the error x had before it;
 // with linear convergence the error after it is about c_t * rho, the rate
 // rho estimated as c_t / c_{t-1} (capped at 1; from step 2 on, step 0's
 // correction being the whole of x).
@@ -592,8 +642,7 @@ __global__ void __launch_bounds__(kRefBlock) refine_residual(const int4 *__restr
                                                              const double *__restrict__ val,
                                                              const double *__restrict__ b,
                                                              const double *__restrict__ x, float *__restrict__ r32,
-                                                             unsigned *__restrict__ d32, sptrsv::Workspace *ws,
-                                                             int32_t n, int t, double tol) {
+                                                             sptrsv::Workspace *ws, int32_t n, int t, double tol) {
     if (refine_done(ws)) return;
     const double c = __longlong_as_double((long long)ws->ratio[t]);
     const double rho = t >= 2 ? fmin(1.0, c / __longlong_as_double((long long)ws->ratio[t - 1])) : 1.0;
@@ -634,7 +683,6 @@ __global__ void __launch_bounds__(kRefBlock) refine_residual(const int4 *__restr
                 if (q + u < e) acc = fma(-vv[u], xx[u], acc);
         }
         r32[i] = (float)acc;
-        d32[i] = Val<float>::kNotReady;
     }
 }
 
@@ -672,7 +720,23 @@ hipError_t launch_tiles(SolveArgs<T> a, int waves, hipStream_t s) {
                                       dim3(64), args, 0, s);
 }
 
-int fill_blocks(int32_t n) { return (int)std::min<int64_t>(2048, ((int64_t)n + 255) / 256); }
+template <typename T>
+hipError_t launch_prepare(const unsigned char *dev, const sptrsv::Layout *lay, const void *b, void *x,
+                          const unsigned *skip, hipStream_t s) {
+    PrepArgs<T> p;
+    p.tiles = reinterpret_cast<const int4 *>(dev + lay->mtiles);
+    p.rows = reinterpret_cast<const int32_t *>(dev + lay->mrow);
+    p.col = reinterpret_cast<const int32_t *>(dev + lay->mcol);
+    p.val = reinterpret_cast<const T *>(dev + lay->mval);
+    p.b = static_cast<const T *>(b);
+    p.bp = reinterpret_cast<T *>(const_cast<unsigned char *>(dev) + lay->bp);
+    p.x = static_cast<typename Val<T>::Bits *>(x);
+    p.ntiles = lay->nmtiles;
+    p.skip = skip;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (lay->nmtiles + 3) / 4));
+    hipLaunchKernelGGL(prepare<T>, dim3(blocks), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
 
 }  // namespace
 
@@ -699,19 +763,16 @@ extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layou
                                    int64_t nitems, int waves, uint64_t wait_limit, const void *b, void *x,
                                    unsigned long long *stamps, int64_t start_slot, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const void *bp = dev + lay->bp;
     hipError_t e;
     if (lay->value_bytes == 4) {
         if (stamps) return (int)hipErrorNotSupported;
-        hipLaunchKernelGGL(fill_not_ready<float>, dim3(fill_blocks(n)), dim3(256), 0, s,
-                           static_cast<unsigned *>(x), n);
-        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-        e = launch_tiles(solve_args<float>(dev, lay, n, nitems, waves, wait_limit, b, x, nullptr), waves, s);
+        if ((e = launch_prepare<float>(dev, lay, b, x, nullptr, s)) != hipSuccess) return (int)e;
+        e = launch_tiles(solve_args<float>(dev, lay, n, nitems, waves, wait_limit, bp, x, nullptr), waves, s);
     } else {
-        hipLaunchKernelGGL(fill_not_ready<double>, dim3(fill_blocks(n)), dim3(256), 0, s,
-                           static_cast<unsigned long long *>(x), n);
-        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        if ((e = launch_prepare<double>(dev, lay, b, x, nullptr, s)) != hipSuccess) return (int)e;
         const SolveArgs<double> a =
-            solve_args<double>(dev, lay, n, nitems, waves, wait_limit, b, x, nullptr, stamps, start_slot);
+            solve_args<double>(dev, lay, n, nitems, waves, wait_limit, bp, x, nullptr, stamps, start_slot);
         e = stamps ? launch_tiles<double, true>(a, waves, s) : launch_tiles<double, false>(a, waves, s);
     }
     return (int)e;
@@ -726,12 +787,14 @@ extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Lay
     float *r32 = reinterpret_cast<float *>(d + lay->r32);
     float *d32 = reinterpret_cast<float *>(d + lay->d32);
     const int grid = (int)std::min<int64_t>(kRefGrid, ((int64_t)n + kRefBlock - 1) / kRefBlock);
-    hipLaunchKernelGGL(refine_init, dim3(std::max(grid, 1)), dim3(kRefBlock), 0, s, b, x, r32,
-                       reinterpret_cast<unsigned *>(d32), ws, n);
+    hipLaunchKernelGGL(refine_init, dim3(std::max(grid, 1)), dim3(kRefBlock), 0, s, b, x, r32, ws, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
-    const SolveArgs<float> a = solve_args<float>(dev, lay, n, nitems, waves, wait_limit, r32, d32, &ws->done);
+    // each step: r' = r32 + M r32 and d32 reset, then the FP32 solve of L' d = r'
+    const SolveArgs<float> a =
+        solve_args<float>(dev, lay, n, nitems, waves, wait_limit, dev + lay->bp, d32, &ws->done);
     for (int t = 0; t < iterations; ++t) {
+        if ((e = launch_prepare<float>(dev, lay, r32, d32, &ws->done, s)) != hipSuccess) return (int)e;
         if ((e = launch_tiles(a, waves, s)) != hipSuccess) return (int)e;
         hipLaunchKernelGGL(refine_update, dim3(grid), dim3(kRefBlock), 0, s, x, d32, ws, n, t);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
@@ -740,8 +803,7 @@ extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Lay
                            reinterpret_cast<const int4 *>(dev + lay->sys), lay->nsys,
                            reinterpret_cast<const int32_t *>(dev + lay->res_rp),
                            reinterpret_cast<const int32_t *>(dev + lay->res_col),
-                           reinterpret_cast<const double *>(dev + lay->res_val), b, x, r32,
-                           reinterpret_cast<unsigned *>(d32), ws, n, t, tol);
+                           reinterpret_cast<const double *>(dev + lay->res_val), b, x, r32, ws, n, t, tol);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
     }
     return 0;
