@@ -377,7 +377,7 @@ def bench_batched(args, torch, sp, workloads, stream):
         return e0.elapsed_time(e1) / reps
 
     best, grid = None, {}
-    for cand in ("plain", "depth4", "depth8", "depth16"):
+    for cand in ("plain", "depth2", "depth4", "depth16"):
         kind, kw = CANDIDATES[cand]
         t0 = time.perf_counter()
         plan.rewrite(kind, **kw)
