@@ -47,6 +47,8 @@ INF = 10**9
 CANDIDATES = {
     "plain": ("none", {}),
     "paper": ("threshold", {"max_width": 4, "max_depth": 64, "max_fill": 0.25}),
+    # the thin-level rule with longer stages
+    "paper256": ("threshold", {"max_width": 4, "max_depth": 256, "max_fill": 1.0}),
     "depth2": ("threshold", {"max_width": INF, "max_depth": 2, "max_fill": 12.0}),
     "depth4": ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 12.0}),
     "depth16": ("threshold", {"max_width": INF, "max_depth": 16, "max_fill": 12.0}),
@@ -57,7 +59,7 @@ CANDIDATES = {
     "depth256": ("threshold", {"max_width": INF, "max_depth": 256, "max_fill": 72.0}),
 }
 # Result of the tuning leg on MI355X (used by --no-tune, e.g. under a profiler).
-TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth256", "powerlaw_4m": "paper",
+TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth256", "powerlaw_4m": "paper256",
          "stencil2d_100": "paper"}
 
 

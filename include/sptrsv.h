@@ -188,6 +188,24 @@ sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *s
  * solve many times.  Errors: as sptrsv_solve, HIP (capture refused). */
 sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, void *stream);
 
+/* How a solve applies the rewritten right-hand side b' = b + M b (Sec. III,
+ * Fig. 3's updated b entries).  The b-terms depend on nothing the solve
+ * computes, so they are taken off the dependent chain in one of two ways:
+ *   SPTRSV_RHS_MPASS  a fully parallel pass over the entries of M before the
+ *                     solve (reads nnz(M) entries);
+ *   SPTRSV_RHS_STAGE  on the rows S of a stage, b'_S = D_S L_SS^-1 b_S (the
+ *                     rewriting eliminates exactly the in-stage couplings), so
+ *                     b' = D y with L_B y = b, L_B the block-diagonal part of
+ *                     L inside the stages: one more solve, by the same kernel,
+ *                     whose chain is one stage deep (the stages are
+ *                     independent) and which reads nnz(L_B) <= nnz(L) entries.
+ *   SPTRSV_RHS_AUTO   (default) the stage solve when nnz(M) > 2 nnz(L_B).
+ * The results agree up to rounding.  Repacks the host image (the upload
+ * becomes stale); the rewrite and its introspection are unchanged.
+ * Errors: ARG (unknown mode), OVERFLOW, OOM. */
+enum { SPTRSV_RHS_AUTO = 0, SPTRSV_RHS_MPASS = 1, SPTRSV_RHS_STAGE = 2 };
+sptrsv_status sptrsv_set_rhs_mode(sptrsv_plan plan, int32_t mode);
+
 /* Value type of the device image: 64 (FP64, the default) or 32.  A plan
  * stored in FP32 keeps every value of L' and M and every diagonal rounded to
  * nearest FP32 and solves in FP32 arithmetic (sptrsv_solve_fp32), with x in
@@ -247,7 +265,10 @@ sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks);
  * bytes: compulsory traffic of one solve in the plan's value type (v = 8
  * bytes for FP64, 4 for FP32): 4 + v per stored entry (int32 column + value,
  * diagonals included) + 8 + 2v per row (row offset, row id, b_i, x_i);
- * gathers of x and b are counted as cache hits. */
+ * gathers of x and b are counted as cache hits.  bytes_rw counts the entries
+ * of L' and those the right-hand-side step reads (nnz_rhs), plus 2v per row
+ * for the M pass (b' written and read) or 8 + 2v per row for the stage
+ * solve. */
 typedef struct {
     int32_t n;
     int32_t levels;      /* levels of L */
@@ -265,6 +286,9 @@ typedef struct {
     int32_t precision;   /* 64 or 32: value type of the device image */
     int64_t seg_tiles;   /* tiles inside segments (runs of narrow levels one
                             wave executes in order) */
+    int32_t rhs_mode;    /* right-hand-side step in use: 0 none (no b-terms),
+                            SPTRSV_RHS_MPASS or SPTRSV_RHS_STAGE */
+    int64_t nnz_rhs;     /* entries it reads: nnz(M), or nnz(L_B) */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

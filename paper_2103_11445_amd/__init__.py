@@ -27,6 +27,7 @@ _LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CSR", 3: "ERR_DIAG", 4: "ERR_OVERFLOW",
           5: "ERR_OOM", 6: "ERR_HIP", 7: "ERR_STATE", 8: "ERR_TIMEOUT"}
 KIND = {"none": 0, "threshold": 1, "explicit": 2, "learned": 3}
+RHS_MODE = {"auto": 0, "mpass": 1, "stage": 2}
 MLP_INPUTS = 6
 MLP_PARAMS = 4673
 INT32_MAX = 2**31 - 1
@@ -54,7 +55,8 @@ class _Info(ctypes.Structure):
                 ("nnz_m", ctypes.c_int64), ("flops", ctypes.c_int64), ("flops_rw", ctypes.c_int64),
                 ("bytes", ctypes.c_int64), ("bytes_rw", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
-                ("precision", ctypes.c_int32), ("seg_tiles", ctypes.c_int64)]
+                ("precision", ctypes.c_int32), ("seg_tiles", ctypes.c_int64),
+                ("rhs_mode", ctypes.c_int32), ("nnz_rhs", ctypes.c_int64)]
 
 
 _lib = None
@@ -88,6 +90,7 @@ def load():
         "sptrsv_solve_refined": (S, [P, P, P, I32, ctypes.c_double, P]),
         "sptrsv_refine_stats": (S, [P, P, P, P]),
         "sptrsv_set_precision": (S, [P, I32]),
+        "sptrsv_set_rhs_mode": (S, [P, I32]),
         "sptrsv_solve_stamped": (S, [P, P, P, P, P]),
         "sptrsv_plan_stamp_levels": (S, [P, P]),
         "sptrsv_plan_level_features": (S, [P, P]),
@@ -235,6 +238,11 @@ class Plan:
 
     def set_wait_limit(self, ticks: int):
         _check(load().sptrsv_set_wait_limit(self._h, int(ticks)))
+
+    def set_rhs_mode(self, mode: str = "auto") -> "Plan":
+        """How b' = b + M b is applied: 'auto', 'mpass' or 'stage' (repacks)."""
+        _check(load().sptrsv_set_rhs_mode(self._h, RHS_MODE[mode]))
+        return self
 
     def set_precision(self, bits: int) -> "Plan":
         """Value type of the device image: 64 or 32 (repacks; upload again)."""

@@ -72,6 +72,18 @@ int launch_waves(const sptrsv::Plan &p) {
     return (int)std::max<int64_t>(1, w);
 }
 
+// Launch shape of the stage system's solve (kRhsStage), else zeros.
+void sub_launch(const sptrsv::Plan &p, int64_t *nitems, int *waves) {
+    *nitems = 0;
+    *waves = 0;
+    if (!p.sub) return;
+    sptrsv::Plan &q = *p.sub;
+    q.cus = p.cus;
+    q.max_waves_per_cu = p.max_waves_per_cu;
+    *nitems = q.ntiles;
+    *waves = launch_waves(q);
+}
+
 bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
     const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
     return pa < pb + bn && pb < pa + an;
@@ -233,8 +245,11 @@ sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *s
     return guarded([&]() -> sptrsv_status {
         if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
         const int waves = launch_waves(*plan);
+        int64_t sn;
+        int sw;
+        sub_launch(*plan, &sn, &sw);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, plan->wait_limit, b, x, nullptr, 0, stream);
+                                          plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, nullptr, 0, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -244,8 +259,11 @@ sptrsv_status sptrsv_solve_fp32(sptrsv_plan plan, const float *b, float *x, void
     return guarded([&]() -> sptrsv_status {
         if (solve_args_ok(plan, b, x, 32, sizeof(float))) return SPTRSV_OK;
         const int waves = launch_waves(*plan);
+        int64_t sn;
+        int sw;
+        sub_launch(*plan, &sn, &sw);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, plan->wait_limit, b, x, nullptr, 0, stream);
+                                          plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, nullptr, 0, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -259,8 +277,12 @@ sptrsv_status sptrsv_solve_refined(sptrsv_plan plan, const double *b, double *x,
         if (!(tol >= 0.0)) return set_err(SPTRSV_ERR_ARG, "tol must be >= 0");
         if (solve_args_ok(plan, b, x, 32, sizeof(double))) return SPTRSV_OK;
         const int waves = launch_waves(*plan);
+        int64_t sn;
+        int sw;
+        sub_launch(*plan, &sn, &sw);
         const int e = sptrsv_launch_refined(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                            plan->ntiles, waves, plan->wait_limit, b, x, iterations, tol, stream);
+                                            plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, iterations, tol,
+                                            stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -305,6 +327,28 @@ sptrsv_status sptrsv_set_precision(sptrsv_plan plan, int32_t bits) {
     });
 }
 
+sptrsv_status sptrsv_set_rhs_mode(sptrsv_plan plan, int32_t mode) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+        if (mode != SPTRSV_RHS_AUTO && mode != SPTRSV_RHS_MPASS && mode != SPTRSV_RHS_STAGE)
+            return set_err(SPTRSV_ERR_ARG, "unknown right-hand-side mode");
+        const int32_t req = mode == SPTRSV_RHS_AUTO ? -1 : mode;
+        if (req == plan->rhs_request) return SPTRSV_OK;
+        const int32_t old = plan->rhs_request;
+        plan->rhs_request = req;
+        plan->uploaded = false;
+        drop_graph(*plan);
+        try {
+            sptrsv::pack(*plan);
+        } catch (...) {
+            plan->rhs_request = old;
+            sptrsv::pack(*plan);
+            throw;
+        }
+        return SPTRSV_OK;
+    });
+}
+
 sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, void *stream) {
     return guarded([&]() -> sptrsv_status {
         if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
@@ -322,8 +366,11 @@ sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, v
             hipStream_t cs = static_cast<hipStream_t>(plan->capture_stream);
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
+            int64_t sn;
+            int sw;
+            sub_launch(*plan, &sn, &sw);
             const int le = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
-                                               plan->ntiles, waves, plan->wait_limit, b, x, nullptr, 0, cs);
+                                               plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, nullptr, 0, cs);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(cs, &g);
             if (le != 0) {
@@ -393,7 +440,13 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->flops_rw = 2 * (o->nnz_rw - p.n + o->nnz_m) + p.n;
     const int64_t vb = p.precision / 8;
     o->bytes = (4 + vb) * o->nnz + (8 + 2 * vb) * (int64_t)p.n;
-    o->bytes_rw = (4 + vb) * (o->nnz_rw + o->nnz_m) + (8 + 2 * vb) * (int64_t)p.n;
+    o->rhs_mode = p.layout.rhs_mode;
+    o->nnz_rhs = p.layout.nnz_rhs;
+    // the solve of L' plus the right-hand-side step: M entries and b, b' per
+    // row (M pass), or a whole solve of L_B (stage solves)
+    o->bytes_rw = (4 + vb) * (o->nnz_rw + o->nnz_rhs) + (8 + 2 * vb) * (int64_t)p.n;
+    if (p.layout.rhs_mode == sptrsv::kRhsMPass) o->bytes_rw += 2 * vb * (int64_t)p.n;
+    if (p.layout.rhs_mode == sptrsv::kRhsStage) o->bytes_rw += (8 + 2 * vb) * (int64_t)p.n;
     o->device_bytes = (int64_t)p.layout.total;
     o->tiles = p.ntiles;
     o->precision = p.precision;
@@ -443,8 +496,11 @@ sptrsv_status sptrsv_solve_stamped(sptrsv_plan plan, const double *b, double *x,
         if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
         if (!stamps) return set_err(SPTRSV_ERR_ARG, "stamps is NULL");
         const int waves = launch_waves(*plan);
+        int64_t sn;
+        int sw;
+        sub_launch(*plan, &sn, &sw);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, plan->wait_limit, b, x,
+                                          plan->ntiles, waves, sn, sw, plan->wait_limit, b, x,
                                           reinterpret_cast<unsigned long long *>(stamps),
                                           plan->ntiles + plan->nseg_tiles, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");

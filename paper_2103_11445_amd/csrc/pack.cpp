@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <memory>
 #include <string>
 
 #include "plan.hpp"
@@ -59,10 +60,63 @@ int seg_lanes_log2(int64_t maxlen) {
 }
 }  // namespace
 
+// The block-diagonal part of L inside the stages: entries (i, j) whose
+// levels belong to the same stage (diagonal included), in CSR.
+static void stage_system(const Plan &p, std::vector<int32_t> &rp, std::vector<int32_t> &ci,
+                         std::vector<double> &val) {
+    const int32_t n = p.n;
+    rp.assign((size_t)n + 1, 0);
+    ci.clear();
+    val.clear();
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t si = p.stage_of_level[(size_t)p.level[(size_t)i]];
+        for (int32_t q = p.rp[(size_t)i]; q < p.rp[(size_t)i + 1]; ++q) {
+            const int32_t j = p.ci[(size_t)q];
+            if (p.stage_of_level[(size_t)p.level[(size_t)j]] != si) continue;
+            ci.push_back(j);
+            val.push_back(p.val[(size_t)q]);
+        }
+        rp[(size_t)i + 1] = (int32_t)ci.size();
+    }
+}
+
+// Choice of the right-hand-side step: none without b-terms; else as
+// requested, or the stage solves when M holds more than twice the entries
+// of L_B (its bytes then dominate the M pass).
+static int32_t choose_rhs(const Plan &p, int64_t nnz_b) {
+    if (p.m_col.empty() || p.is_sub) return kRhsNone;
+    if (p.rhs_request == kRhsMPass || p.rhs_request == kRhsStage) return p.rhs_request;
+    return (int64_t)p.m_col.size() > 2 * nnz_b ? kRhsStage : kRhsMPass;
+}
+
 void pack(Plan &p) {
     const int32_t n = p.n;
     if ((int64_t)n + kRing > INT32_MAX)
         throw Error{SPTRSV_ERR_OVERFLOW, "n too large for the device encoding"};
+    // ---- right-hand-side step
+    int32_t rhs_mode = kRhsNone;
+    int64_t nnz_rhs = 0;
+    p.sub.reset();
+    if (!p.m_col.empty() && !p.is_sub) {
+        std::vector<int32_t> brp, bci;
+        std::vector<double> bval;
+        stage_system(p, brp, bci, bval);
+        rhs_mode = choose_rhs(p, (int64_t)bci.size());
+        if (rhs_mode == kRhsStage) {
+            std::unique_ptr<Plan> sub(new Plan());
+            sub->is_sub = true;
+            sub->precision = p.precision;
+            analyse(*sub, n, brp.data(), bci.data(), bval.data());
+            sub->upper = p.upper;
+            sptrsv_policy none{};
+            none.kind = SPTRSV_POLICY_NONE;
+            rewrite(*sub, none);  // packs the stage system's image
+            nnz_rhs = (int64_t)bci.size();
+            p.sub = std::move(sub);
+        } else {
+            nnz_rhs = (int64_t)p.m_col.size();
+        }
+    }
     std::vector<int64_t> len((size_t)n);
     for (int32_t i = 0; i < n; ++i) len[(size_t)i] = p.lp_ptr[(size_t)i + 1] - p.lp_ptr[(size_t)i] - 1;
 
@@ -173,7 +227,7 @@ void pack(Plan &p) {
     std::vector<int32_t> mslot_row((size_t)n);
     std::vector<Tile> mtiles;
     int64_t mchunks = 0;
-    {
+    if (rhs_mode == kRhsMPass) {
         int32_t cnt[kBins] = {0};
         auto mlen = [&](int32_t i) { return p.m_ptr[(size_t)i + 1] - p.m_ptr[(size_t)i]; };
         auto row_at = [&](int32_t d) { return p.upper ? n - 1 - d : d; };  // plan row of caller index d
@@ -241,7 +295,9 @@ void pack(Plan &p) {
     Ly.bp = off;
     off = align256(off + (size_t)n * vb);
     Ly.nmtiles = (int64_t)mtiles.size();
-    if (f32) {
+    Ly.rhs_mode = rhs_mode;
+    Ly.nnz_rhs = nnz_rhs;
+    if (f32 && !p.is_sub) {
         Ly.nsys = (int32_t)p.sys_n.size();
         for (size_t j = 0; j < p.sys_n.size(); ++j) {
             // a system's block of the union holds k identical copies
@@ -263,9 +319,15 @@ void pack(Plan &p) {
         Ly.d32 = off;
         off = align256(off + (size_t)n * 4);
     }
+    if (p.sub) {
+        Ly.sub = off;
+        Ly.sub_layout = &p.sub->layout;
+        off = align256(off + p.sub->layout.total);
+    }
     Ly.total = off;
 
     p.image.assign(Ly.total, 0);
+    if (p.sub) std::copy(p.sub->image.begin(), p.sub->image.end(), p.image.begin() + (ptrdiff_t)Ly.sub);
     unsigned char *img = p.image.data();
     int32_t *trow = reinterpret_cast<int32_t *>(img + Ly.rows);
     int32_t *tcol = reinterpret_cast<int32_t *>(img + Ly.tcol);
@@ -354,7 +416,7 @@ void pack(Plan &p) {
             });
         }
     }
-    {
+    if (rhs_mode == kRhsMPass) {
         // M tiles: b-terms (device index of b_j, coefficient M_ij)
         int32_t *mdesc = reinterpret_cast<int32_t *>(img + Ly.mtiles);
         int32_t *mrow = reinterpret_cast<int32_t *>(img + Ly.mrow);
@@ -379,7 +441,7 @@ void pack(Plan &p) {
             }
         }
     }
-    if (f32) {
+    if (f32 && !p.is_sub) {
         // the caller's matrices in FP64 (device indices) for the residual
         int32_t *sys = reinterpret_cast<int32_t *>(img + Ly.sys);
         int32_t *rrp = reinterpret_cast<int32_t *>(img + Ly.res_rp);

@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -26,11 +27,26 @@ constexpr int kSegDepth = 4;      // segment software-pipeline depth; segments h
 
 constexpr int kMaxRefine = 16;    // refinement iterations per call (slots in the workspace)
 
+// How the solve applies the rewritten right-hand side b' = b + M b.
+enum RhsMode : int32_t {
+    kRhsNone = 0,   // no b-terms: the solve reads b
+    kRhsMPass = 1,  // a parallel SpMV over M tiles writes b' before the solve
+    kRhsStage = 2,  // b' = D y with L_B y = b, L_B the block-diagonal part of L
+                    // inside the stages (stage_of_level equal): one more solve
+                    // whose chain is the depth of a stage, reading nnz(L_B)
+                    // entries instead of nnz(M)
+};
+
+struct Layout;
+
 // Device image layout: byte offsets of each section inside the caller's
 // buffer.  Sections are 256-byte aligned.  Values (diag, tval, sval, sdiag)
 // are FP64, or FP32 in a plan stored in FP32 (value_bytes 4).
 struct Layout {
     int value_bytes = 8;
+    int32_t rhs_mode = kRhsNone;
+    size_t sub = 0;               // kRhsStage: offset of the stage system's image
+    const Layout *sub_layout = nullptr;
     size_t workspace = 0;  // Workspace block
     size_t tiles = 0;      // int4[nitems]: wide tile {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
                            //   or segment {first segment tile, count, 0, 1<<31}
@@ -48,8 +64,9 @@ struct Layout {
     size_t mrow = 0;       // int32[n]  device row of each M-tile slot
     size_t mcol = 0;       // int32[64*mchunks] device index of b_j (INT32_MIN pad)
     size_t mval = 0;       // double[64*mchunks] M_ij
-    size_t bp = 0;         // double[n] b' (device indices), written by the pass
+    size_t bp = 0;         // double[n] b' (kRhsMPass) or y (kRhsStage), device indices
     int64_t nmtiles = 0;
+    int64_t nnz_rhs = 0;   // entries the right-hand-side step reads (M, or L_B)
     // FP32 plans only: what iterative refinement needs next to the FP32
     // schedule -- the caller's matrices in FP64 for the residual, and two
     // FP32 vectors (residual, correction) indexed like b and x
@@ -93,6 +110,11 @@ struct Plan {
     // value type of the device image: 64 (FP64) or 32 (FP32 storage and
     // arithmetic, refined to FP64 by sptrsv_solve_refined)
     int precision = 64;
+    // right-hand-side step: requested (-1 = chosen from the sizes of M and
+    // L_B) and, for kRhsStage, the plan of the stage system L_B
+    int32_t rhs_request = -1;
+    std::unique_ptr<struct Plan> sub;
+    bool is_sub = false;  // a stage system (no residual data, no sub-plan)
     std::vector<int32_t> rp, ci;
     std::vector<double> val;
     std::vector<int32_t> level;  // level of each row of L
@@ -162,10 +184,11 @@ void pack(Plan &p);
 // With stamps (FP64 plans only), the instrumented kernel also writes the
 // real-time clock (100 MHz) as every item and every segment tile completes
 // (slots [0, nitems) and nitems + segment tile), and its start at start_slot.
+// sub_nitems / sub_waves: the stage system's solve (kRhsStage).
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay,
-                                   int32_t n, int64_t nitems, int waves, uint64_t wait_limit,
-                                   const void *b, void *x, unsigned long long *stamps, int64_t start_slot,
-                                   void *stream);
+                                   int32_t n, int64_t nitems, int waves, int64_t sub_nitems, int sub_waves,
+                                   uint64_t wait_limit, const void *b, void *x, unsigned long long *stamps,
+                                   int64_t start_slot, void *stream);
 // mlp.hip -- cost model kernels (FP32 parameter vector of 4673 floats)
 extern "C" size_t sptrsv_launch_mlp_workspace(int32_t m);
 extern "C" int sptrsv_launch_mlp_forward(const float *params, const float *X, float *Y, int32_t m, void *stream);
@@ -176,7 +199,7 @@ extern "C" int sptrsv_launch_mlp_adam(float *params, const float *grad, float *m
 // FP32 plans: `iterations` refinement steps on x (FP64), all on stream; the
 // steps after convergence (correction <= tol) skip their work on the device.
 extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay,
-                                     int32_t n, int64_t nitems, int waves, uint64_t wait_limit,
-                                     const double *b, double *x, int iterations, double tol,
-                                     void *stream);
+                                     int32_t n, int64_t nitems, int waves, int64_t sub_nitems, int sub_waves,
+                                     uint64_t wait_limit, const double *b, double *x, int iterations,
+                                     double tol, void *stream);
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu);

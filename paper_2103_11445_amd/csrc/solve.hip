@@ -25,8 +25,13 @@
 //     ahead, b / external-x gathers kDepth/2 tiles ahead, so the critical
 //     path waits only on LDS and on loads issued several tiles before.
 //   * The rewritten right-hand side b' = b + M b depends on nothing the
-//     solve computes: a fully parallel pass (prepare) computes it, and resets
-//     x, before the dependent solve, whose terms are then x-terms only.
+//     solve computes, so the solve's tiles hold x-terms only and b' comes
+//     from a step before it: either a fully parallel pass over M (prepare),
+//     or -- since b'_S = D_S L_SS^-1 b_S on the rows S of a stage -- a solve
+//     of the block-diagonal system L_B (the stages' diagonal blocks of L) by
+//     the same kernel, whose chain is one stage deep and which reads nnz(L_B)
+//     entries instead of nnz(M); the main solve then reads y and scales it
+//     by the diagonal.
 //   * The same kernels run in FP64 or, for plans stored in FP32, in FP32
 //     (values, arithmetic and x; the readiness pattern is then an FP32
 //     signalling NaN); iterative refinement adds an FP64 residual and an
@@ -90,7 +95,8 @@ struct SolveArgs {
     const unsigned *skip;  // refinement: the grid returns at once if *skip (NULL: never)
     unsigned long long *stamps;  // timed solves: completion clock of every item and segment tile
     long long start_slot;        // stamps[start_slot]: the clock when the grid started
-    const T *b;  // b' = b + M b (written by prepare)
+    const T *b;  // b' = b + M b (written by prepare), y (b' = diag * y), or b
+    int bscale;  // the constants are y: b'_i = diag_i * y_i
     T *x;
     long long nitems;
     long long waves;
@@ -242,6 +248,17 @@ __device__ inline int load_item(const SolveArgs<T> &a, long long i, int lane) {
 __device__ inline int4 unpack_item(int w) {
     return make_int4(__builtin_amdgcn_readlane(w, 0), __builtin_amdgcn_readlane(w, 1),
                      __builtin_amdgcn_readlane(w, 2), __builtin_amdgcn_readlane(w, 3));
+}
+
+// x (and y of the stage system) := not ready.
+template <typename T>
+__global__ void fill_not_ready(typename Val<T>::Bits *__restrict__ x, typename Val<T>::Bits *__restrict__ y,
+                               int32_t n, const unsigned *skip) {
+    if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        x[i] = Val<T>::kNotReady;
+        if (y) y[i] = Val<T>::kNotReady;
+    }
 }
 
 // ---------------------------------------------------------------- prepare --
@@ -396,6 +413,7 @@ __device__ inline void seg_gather(const SolveArgs<T> &a, SegSlot<T> &S) {
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) S.g[c] = load_cached(gather_addr(a, seg_col(S, c)));
     S.bi = a.b[S.rm.x >= 0 ? S.rm.x : 0];
+    if (a.bscale) S.bi *= S.diag;
 }
 
 template <typename T>
@@ -494,7 +512,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
             g[c] = load_cached(gather_addr(a, col[c]));
         }
         const bool lead = tile_lead(cur.d, lane);
-        const T bi = a.b[lead ? cur.row : 0];
+        const T braw = a.b[lead ? cur.row : 0];
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         // 2. the next tile's terms and the descriptor after it
@@ -537,6 +555,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         // 5. row sums across the row's lanes, then x_i
         acc = group_sum(acc, cur.d.w & 0xff);
         if (lead) {
+            const T bi = a.bscale ? braw * cur.diag : braw;
             const T xi = (bi + acc) / cur.diag;
             __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + cur.row, Val<T>::bits(xi),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -705,6 +724,7 @@ SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int
     a.ws = reinterpret_cast<sptrsv::Workspace *>(const_cast<unsigned char *>(dev) + lay->workspace);
     a.skip = skip;
     a.b = static_cast<const T *>(b);
+    a.bscale = 0;
     a.x = static_cast<T *>(x);
     a.nitems = nitems;
     a.waves = waves;
@@ -738,6 +758,43 @@ hipError_t launch_prepare(const unsigned char *dev, const sptrsv::Layout *lay, c
     return hipGetLastError();
 }
 
+int fill_blocks(int32_t n) { return (int)std::min<int64_t>(2048, ((int64_t)n + 255) / 256); }
+
+// One solve of L x = b in the plan's value type: the right-hand-side step of
+// the plan's mode, then the dependent solve.  With kRhsStage the stage
+// system runs first (into y = the image's bp vector) and shares the main
+// workspace, so a failed wait in either is reported by the same status word.
+template <typename T, bool kStamp>
+hipError_t solve_once(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n, int64_t nitems, int waves,
+                      int64_t sub_nitems, int sub_waves, uint64_t wait_limit, const void *b, void *x,
+                      const unsigned *skip, unsigned long long *stamps, int64_t start_slot, hipStream_t s) {
+    using B = typename Val<T>::Bits;
+    unsigned char *d = const_cast<unsigned char *>(dev);
+    hipError_t e;
+    const void *rhs = b;
+    int bscale = 0;
+    if (lay->rhs_mode == sptrsv::kRhsMPass) {
+        if ((e = launch_prepare<T>(dev, lay, b, x, skip, s)) != hipSuccess) return e;
+        rhs = d + lay->bp;
+    } else {
+        B *y = lay->rhs_mode == sptrsv::kRhsStage ? reinterpret_cast<B *>(d + lay->bp) : nullptr;
+        hipLaunchKernelGGL(fill_not_ready<T>, dim3(fill_blocks(n)), dim3(256), 0, s, static_cast<B *>(x), y, n,
+                           skip);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (y) {
+            SolveArgs<T> sa = solve_args<T>(dev + lay->sub, lay->sub_layout, n, sub_nitems, sub_waves, wait_limit,
+                                            b, y, skip);
+            sa.ws = reinterpret_cast<sptrsv::Workspace *>(d + lay->workspace);
+            if ((e = launch_tiles<T, false>(sa, sub_waves, s)) != hipSuccess) return e;
+            rhs = y;
+            bscale = 1;
+        }
+    }
+    SolveArgs<T> a = solve_args<T>(dev, lay, n, nitems, waves, wait_limit, rhs, x, skip, stamps, start_slot);
+    a.bscale = bscale;
+    return launch_tiles<T, kStamp>(a, waves, s);
+}
+
 }  // namespace
 
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
@@ -760,27 +817,26 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
 }
 
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
-                                   int64_t nitems, int waves, uint64_t wait_limit, const void *b, void *x,
-                                   unsigned long long *stamps, int64_t start_slot, void *stream) {
+                                   int64_t nitems, int waves, int64_t sub_nitems, int sub_waves, uint64_t wait_limit,
+                                   const void *b, void *x, unsigned long long *stamps, int64_t start_slot,
+                                   void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const void *bp = dev + lay->bp;
-    hipError_t e;
     if (lay->value_bytes == 4) {
         if (stamps) return (int)hipErrorNotSupported;
-        if ((e = launch_prepare<float>(dev, lay, b, x, nullptr, s)) != hipSuccess) return (int)e;
-        e = launch_tiles(solve_args<float>(dev, lay, n, nitems, waves, wait_limit, bp, x, nullptr), waves, s);
-    } else {
-        if ((e = launch_prepare<double>(dev, lay, b, x, nullptr, s)) != hipSuccess) return (int)e;
-        const SolveArgs<double> a =
-            solve_args<double>(dev, lay, n, nitems, waves, wait_limit, bp, x, nullptr, stamps, start_slot);
-        e = stamps ? launch_tiles<double, true>(a, waves, s) : launch_tiles<double, false>(a, waves, s);
+        return (int)solve_once<float, false>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, b, x,
+                                             nullptr, nullptr, 0, s);
     }
-    return (int)e;
+    if (stamps)
+        return (int)solve_once<double, true>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, b, x,
+                                             nullptr, stamps, start_slot, s);
+    return (int)solve_once<double, false>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, b, x,
+                                          nullptr, nullptr, 0, s);
 }
 
 extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
-                                     int64_t nitems, int waves, uint64_t wait_limit, const double *b,
-                                     double *x, int iterations, double tol, void *stream) {
+                                     int64_t nitems, int waves, int64_t sub_nitems, int sub_waves,
+                                     uint64_t wait_limit, const double *b, double *x, int iterations, double tol,
+                                     void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned char *d = const_cast<unsigned char *>(dev);
     sptrsv::Workspace *ws = reinterpret_cast<sptrsv::Workspace *>(d + lay->workspace);
@@ -790,12 +846,11 @@ extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Lay
     hipLaunchKernelGGL(refine_init, dim3(std::max(grid, 1)), dim3(kRefBlock), 0, s, b, x, r32, ws, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
-    // each step: r' = r32 + M r32 and d32 reset, then the FP32 solve of L' d = r'
-    const SolveArgs<float> a =
-        solve_args<float>(dev, lay, n, nitems, waves, wait_limit, dev + lay->bp, d32, &ws->done);
+    // each step: the FP32 solve of L d = r32 (right-hand-side step included)
     for (int t = 0; t < iterations; ++t) {
-        if ((e = launch_prepare<float>(dev, lay, r32, d32, &ws->done, s)) != hipSuccess) return (int)e;
-        if ((e = launch_tiles(a, waves, s)) != hipSuccess) return (int)e;
+        if ((e = solve_once<float, false>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, r32, d32,
+                                          &ws->done, nullptr, 0, s)) != hipSuccess)
+            return (int)e;
         hipLaunchKernelGGL(refine_update, dim3(grid), dim3(kRefBlock), 0, s, x, d32, ws, n, t);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
         if (t + 1 == iterations) break;

@@ -66,7 +66,9 @@ def compare_with_oracle(sp, s, pol):
     assert info["flops"] == oracle.flops(s.row_ptr)
     assert info["flops_rw"] == oracle.flops(o["lp"][0], o["m"][0])
     assert info["bytes"] == 12 * s.nnz + 24 * s.n
-    assert info["bytes_rw"] == 12 * (info["nnz_rw"] + info["nnz_m"]) + 24 * s.n
+    extra = {0: 0, 1: 16 * s.n, 2: 24 * s.n}[info["rhs_mode"]]
+    assert info["bytes_rw"] == 12 * (info["nnz_rw"] + info["nnz_rhs"]) + 24 * s.n + extra
+    assert info["nnz_rhs"] == (0 if info["nnz_m"] == 0 else info["nnz_rhs"])
     return plan, o
 
 
@@ -326,7 +328,8 @@ def test_fp32_plan_keeps_the_schedule(sp):
         assert i64[k] == i32[k], k
     n = i64["n"]
     assert i32["bytes"] == 8 * i32["nnz"] + 16 * n
-    assert i32["bytes_rw"] == 8 * (i32["nnz_rw"] + i32["nnz_m"]) + 16 * n
+    extra = {0: 0, 1: 8 * n, 2: 16 * n}[i32["rhs_mode"]]
+    assert i32["bytes_rw"] == 8 * (i32["nnz_rw"] + i32["nnz_rhs"]) + 16 * n + extra
     assert i64["bytes"] == 12 * i64["nnz"] + 24 * n
     assert np.array_equal(p64.levels(1), p32.levels(1))
     for a, b in zip(p64.export()[0] + p64.export()[1], p32.export()[0] + p32.export()[1]):
@@ -430,3 +433,34 @@ def test_learned_policy_needs_a_model(sp):
     assert sp.STATUS[lib.sptrsv_mlp_forward(None, None, None, 0, None)] == "OK"   # nothing to do
     assert sp.STATUS[lib.sptrsv_mlp_forward(None, None, None, 4, None)] == "ERR_ARG"
     assert sp.STATUS[lib.sptrsv_mlp_adam(None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, None)] == "ERR_ARG"
+
+
+# ------------------------------------------------ right-hand-side modes --
+
+def test_rhs_modes(sp):
+    """The two ways of applying b' = b + M b: the M pass reads nnz(M)
+    entries, the stage solve the entries of L inside the stages (counted
+    here from the stage of every level); the rewrite itself is unchanged."""
+    s = wl.banded(4000, 200, 8, 24, seed=9)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", max_width=INF, max_depth=16, max_fill=12.0)
+    lp0, m0 = plan.export()
+    sol, _ = plan.stages()
+    lev = plan.levels(0)
+    st = sol[lev]
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    nnz_b = int(np.sum(st[rows] == st[s.col_idx]))
+    assert plan.info()["rhs_mode"] == 2 and plan.info()["nnz_rhs"] == nnz_b   # auto: M is large here
+    plan.set_rhs_mode("mpass")
+    i = plan.info()
+    assert i["rhs_mode"] == 1 and i["nnz_rhs"] == i["nnz_m"]
+    plan.set_rhs_mode("stage")
+    assert plan.info()["rhs_mode"] == 2
+    for a, b in zip(plan.export()[0] + plan.export()[1], lp0 + m0):
+        assert np.array_equal(a, b)
+    plain = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    assert plain.info()["rhs_mode"] == 0 and plain.info()["nnz_rhs"] == 0
+    lib = sp.load()
+    assert sp.STATUS[lib.sptrsv_set_rhs_mode(plan._h, 7)] == "ERR_ARG"
+    # the mode survives a rewrite, and FP32 packing carries the stage system too
+    plan.set_precision(32).rewrite("threshold", max_width=INF, max_depth=8, max_fill=12.0)
+    assert plan.info()["rhs_mode"] == 2
