@@ -102,21 +102,56 @@ def level_times(stamps: np.ndarray, level: np.ndarray, nlev: int) -> np.ndarray:
     return np.diff(front).astype(np.float64) / TICKS_PER_US
 
 
-def measure_levels(torch, plan: Plan, b, x, reps: int = 3):
+def rhs_share(plan: Plan, row_ptr, col_idx) -> np.ndarray:
+    """Share of the right-hand-side step (the pass over M, or the solve of
+    the stages' diagonal blocks) that each executed level accounts for: its
+    rows' entries in that step over all of them (zeros without one)."""
+    info = plan.info()
+    nl = info["levels_rw"]
+    if info["rhs_mode"] == 0 or info["nnz_rhs"] == 0:
+        return np.zeros(nl)
+    lev_rw = plan.levels(1)
+    if info["rhs_mode"] == 1:
+        _, (m_ptr, _, _) = plan.export()
+        per_row = np.diff(m_ptr).astype(np.float64)
+    else:
+        sol, _ = plan.stages()
+        st = sol[plan.levels(0)]
+        rp = np.asarray(row_ptr, dtype=np.int64)
+        rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+        per_row = np.bincount(rows, weights=(st[rows] == st[np.asarray(col_idx)]).astype(np.float64),
+                              minlength=rp.size - 1)
+    w = np.bincount(lev_rw, weights=per_row, minlength=nl)
+    return w / max(w.sum(), 1.0)
+
+
+def measure_levels(torch, plan: Plan, b, x, row_ptr, col_idx, reps: int = 3, with_rhs: bool = False):
     """Features and median level times of ``plan`` (uploaded) over ``reps``
-    instrumented solves."""
+    instrumented solves.  A level's time is its growth of the completion
+    frontier of the dependent solve; with ``with_rhs`` it also carries its
+    share (rhs_share) of the right-hand-side step, taken as the call's event
+    time minus the span of the stamps, so that the labels of one call sum to
+    its time."""
     info = plan.info()
     stamps = torch.empty(info["tiles"] + info["seg_tiles"] + 1, dtype=torch.int64, device=b.device)
     lv = plan.stamp_levels()
+    share = rhs_share(plan, row_ptr, col_idx) if with_rhs else np.zeros(info["levels_rw"])
+    stream = torch.cuda.current_stream()
     times = []
     plan.solve_stamped(b, x, stamps)  # warm-up
     for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         plan.solve_stamped(b, x, stamps)
-        times.append(level_times(stamps.cpu().numpy(), lv, info["levels_rw"]))
+        e1.record(stream)
+        e1.synchronize()
+        t = level_times(stamps.cpu().numpy(), lv, info["levels_rw"])
+        rest_us = max(0.0, 1000.0 * e0.elapsed_time(e1) - float(t.sum()))
+        times.append(t + rest_us * share)
     return plan.level_features(), np.median(np.stack(times), axis=0)
 
 
-def collect(torch, seeds, log_every: int = 1, budget_s: float = float("inf")):
+def collect(torch, seeds, log_every: int = 1, budget_s: float = float("inf"), with_rhs: bool = False):
     """Training samples (features, log level time) from the corpus matrices
     drawn from ``seeds``, each measured under :func:`label_policies`; stops
     early once ``budget_s`` seconds have passed.  Returns (X, y, matrices
@@ -137,7 +172,7 @@ def collect(torch, seeds, log_every: int = 1, budget_s: float = float("inf")):
         rows = 0
         for kind, kw in label_policies(seed):
             _rewrite(plan, kind, kw, nlev).upload()
-            f, t = measure_levels(torch, plan, b, x)
+            f, t = measure_levels(torch, plan, b, x, s.row_ptr, s.col_idx, with_rhs=with_rhs)
             if plan.check() != 0:
                 raise RuntimeError(f"solve of corpus matrix {seed} timed out")
             X.append(f)
@@ -297,6 +332,8 @@ def main(argv=None):
     t.add_argument("--heldout", type=int, default=40, help="held-out matrices evaluated after training")
     t.add_argument("--steps", type=int, default=4000)
     t.add_argument("--budget", type=float, default=float("inf"), help="seconds for collecting labels")
+    t.add_argument("--rhs-share", action="store_true",
+                   help="charge each level its share of the right-hand-side step in the labels")
     t.add_argument("--report", default=None, help="JSON file for the evaluation")
     e = sub.add_parser("evaluate")
     e.add_argument("--model", default=DEFAULT_MODEL)
@@ -309,12 +346,13 @@ def main(argv=None):
     load()
     if args.cmd == "train":
         t0 = time.perf_counter()
-        X, y, used = collect(torch, [TRAIN_SEED + m for m in range(args.train)], budget_s=args.budget)
+        X, y, used = collect(torch, [TRAIN_SEED + m for m in range(args.train)], budget_s=args.budget,
+                             with_rhs=args.rhs_share)
         t_collect = time.perf_counter() - t0
         log(f"[collect] {X.shape[0]} samples from {used} matrices in {t_collect:.0f} s")
         params, hist = train(torch, X, y, steps=args.steps)
         meta = {"train_matrices": used, "train_seed": TRAIN_SEED, "samples": int(X.shape[0]),
-                "n_range": [1e4, 1e6],
+                "n_range": [1e4, 1e6], "rhs_share": bool(args.rhs_share),
                 "steps": args.steps, "loss": hist, "label": "ln(level time in microseconds)",
                 "collect_s": t_collect}
         save_model(args.out, params, meta)
