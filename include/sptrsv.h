@@ -172,16 +172,19 @@ sptrsv_status sptrsv_device_bytes(sptrsv_plan plan, size_t *bytes);
 sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void *stream);
 
 /* Solves L x = b (device arrays of n doubles, b != x, neither overlapping
- * the plan buffer) with the uploaded schedule: enqueues one fill of x and one
- * cooperative solve kernel on stream and returns without waiting.  Every
- * row waits only for the rows it still depends on (per-row readiness, in
- * level order), so the level structure bounds the critical path.  Numerical problems are not
- * reported (zero diagonals were rejected by analyse); a dependency wait
- * that exceeds the wait limit is reported by sptrsv_check.  Errors: ARG,
- * STATE (not uploaded, stale, or stored in FP32), HIP. */
+ * the plan buffer) with the uploaded schedule: enqueues on stream the
+ * right-hand-side step (see sptrsv_set_rhs_mode: one pass over M, or a fill
+ * and one cooperative solve of the stage system; a fill of x without
+ * b-terms) and one cooperative solve kernel, and returns without waiting.
+ * Every row waits only for the rows it still depends on (per-row readiness,
+ * in level order), so the level structure bounds the critical path.
+ * Numerical problems are not reported (zero diagonals were rejected by
+ * analyse); a dependency wait that exceeds the wait limit is reported by
+ * sptrsv_check.  Errors: ARG, STATE (not uploaded, stale, or stored in
+ * FP32), HIP. */
 sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *stream);
 
-/* As sptrsv_solve (FP64 plans), through a HIP graph: the fill and solve launches are
+/* As sptrsv_solve (FP64 plans), through a HIP graph: its launches are
  * captured once (on a stream the plan owns) for these b and x and replayed
  * on `stream` by later calls with the same pointers (a different b, x, launch
  * shape, rewrite or upload captures again).  For callers that replay one
