@@ -61,6 +61,7 @@ CANDIDATES = {
 # Result of the tuning leg on MI355X (used by --no-tune, e.g. under a profiler).
 TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth256", "powerlaw_4m": "paper256",
          "stencil2d_100": "paper"}
+TUNED_TILING = {"stencil3d_128": 4, "banded_1m": 4, "powerlaw_4m": 2, "stencil2d_100": 4}
 
 
 def log(*a):
@@ -79,7 +80,7 @@ def kernel_sources_hash() -> str:
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2103_11445_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    h.update(json.dumps({n: CANDIDATES[TUNED[n]] for n in LARGE}, sort_keys=True).encode())
+    h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n]] for n in LARGE}, sort_keys=True).encode())
     return h.hexdigest()
 
 
@@ -204,11 +205,16 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     # ---- tuning leg
-    plans, chosen, tuning = {}, {}, {}
+    plans, chosen, tuning, tiling = {}, {}, {}, {}
     for n in names:
         if args.no_tune:
             chosen[n] = TUNED.get(n, "paper")
+            tiling[n] = TUNED_TILING.get(n, 4)
             plans[n], h = make_plan(n, chosen[n])
+            if tiling[n] != 4:
+                plans[n].set_tiling(tiling[n])
+                plans[n]._buf = None
+                plans[n].upload()
             host[n].update(h)
             continue
         best = None
@@ -230,6 +236,22 @@ def main():
                 p.close()
         _, plans[n], chosen[n], h = best
         host[n].update(h)
+        # row-to-wavefront tiling of the chosen plan
+        tiling[n] = 4
+        best_ms = best[0]
+        for tpl in (2, 8):
+            p = plans[n].set_tiling(tpl)
+            p._buf = None
+            p.upload()
+            ms = time_solves(p, n, 2)
+            tuning[n][f"{chosen[n]}/t{tpl}"] = {"ms": ms, "levels_rw": p.info()["levels_rw"],
+                                               "entries": tuning[n][chosen[n]]["entries"], "status": p.check()}
+            log(f"[tune] {n} {chosen[n]} terms/lane {tpl}: {ms:.3f} ms")
+            if ms < best_ms:
+                best_ms, tiling[n] = ms, tpl
+        plans[n].set_tiling(tiling[n])
+        plans[n]._buf = None
+        plans[n].upload()
 
     # ---- timed leg
     def run(plan_set, steps, tag):
@@ -277,7 +299,8 @@ def main():
             "n": i["n"], "nnz": i["nnz"], "levels": i["levels"], "stages": i["stages"],
             "levels_rw": i["levels_rw"], "entries_rw": i["nnz_rw"] + i["nnz_m"],
             "flops": i["flops"], "flops_rw": i["flops_rw"], "bytes": i["bytes"],
-            "bytes_rw": i["bytes_rw"], "policy": chosen[n], "ms_per_solve": per[n],
+            "bytes_rw": i["bytes_rw"], "policy": chosen[n], "terms_per_lane": tiling[n],
+            "rhs_mode": i["rhs_mode"], "ms_per_solve": per[n],
             "solves_per_s": 1000.0 / per[n],
             "plan_gbps": i["bytes_rw"] / (per[n] * 1e-3) / 1e9,
             "effective_gbps": i["bytes"] / (per[n] * 1e-3) / 1e9,
@@ -309,7 +332,7 @@ def main():
     # measured HBM bytes (rocprofv3 counters, calibrated) of the same kernel,
     # plans and workload; only valid for the tuned policies it was taken with
     traffic = None
-    if args.workload == "large" and all(chosen[n] == TUNED[n] for n in names):
+    if args.workload == "large" and all(chosen[n] == TUNED[n] and tiling[n] == TUNED_TILING[n] for n in names):
         traffic = profiled_traffic()
     if traffic is not None:
         for n in names:
@@ -342,8 +365,9 @@ def main():
 def bench_batched(args, torch, sp, workloads, stream):
     """64 systems of uneven size (n log-uniform in [1e3, 2e5], four families)
     with 1, 4, 8 or 32 right-hand sides each, solved by one graph-captured
-    launch of one batched plan; the rewrite depth and waves per CU are picked
-    by measuring a small grid (the autotuner).  Compared with solving every
+    launch of one batched plan; the rewrite depth, the waves per CU and the
+    row-to-wavefront tiling (terms per lane) are picked by measuring
+    a small grid (the autotuner).  Compared with solving every
     system separately, column by column, on the plain level-set schedule.
     value = right-hand sides solved per second."""
     corp = workloads.batch_corpus(64)
@@ -378,23 +402,30 @@ def bench_batched(args, torch, sp, workloads, stream):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    # the autotuner: rewrite depth x row-to-wavefront tiling (terms per lane)
+    # x waves per CU, each point measured
     best, grid = None, {}
-    for cand in ("plain", "depth2", "depth4", "depth16"):
+    for cand in ("plain", "depth2", "depth4"):
         kind, kw = CANDIDATES[cand]
         t0 = time.perf_counter()
         plan.rewrite(kind, **kw)
         t_rw = time.perf_counter() - t0
-        plan.upload()
-        for wpc in (1, 2, 4):
-            plan.set_launch(wpc)
-            ms = timed(lambda: plan.solve_graph(bcat, x), 2)
-            grid[f"{cand}/wpc{wpc}"] = round(ms, 4)
-            log(f"[tune] {cand} wpc {wpc}: {ms:.3f} ms (rewrite {t_rw:.1f} s)")
-            if best is None or ms < best[0]:
-                best = (ms, cand, wpc)
-    _, cand, wpc = best
+        for tpl in (2, 4, 8):
+            plan.set_tiling(tpl)
+            plan._buf = None
+            plan.upload()
+            for wpc in (2, 4):
+                plan.set_launch(wpc)
+                ms = timed(lambda: plan.solve_graph(bcat, x), 2)
+                grid[f"{cand}/t{tpl}/wpc{wpc}"] = round(ms, 4)
+                log(f"[tune] {cand} terms/lane {tpl} wpc {wpc}: {ms:.3f} ms (rewrite {t_rw:.1f} s)")
+                if best is None or ms < best[0]:
+                    best = (ms, cand, tpl, wpc)
+    _, cand, tpl, wpc = best
     kind, kw = CANDIDATES[cand]
-    plan.rewrite(kind, **kw).upload()
+    plan.rewrite(kind, **kw).set_tiling(tpl)
+    plan._buf = None
+    plan.upload()
     plan.set_launch(wpc)
     for _ in range(args.warmup):
         plan.solve_graph(bcat, x)
@@ -410,7 +441,7 @@ def bench_batched(args, torch, sp, workloads, stream):
             errs.append(errors(got[off:off + s_.n * k].reshape(s_.n, k), r_.reshape(s_.n, k)))
             off += s_.n * k
         err = (max(e[0] for e in errs), max(e[1] for e in errs))
-    log(f"[timed] {cand} wpc {wpc}: {ms:.3f} ms per batch, status {status}, error {err}")
+    log(f"[timed] {cand} terms/lane {tpl} wpc {wpc}: {ms:.3f} ms per batch, status {status}, error {err}")
     # comparator: the plain schedule, one system and one right-hand side at a time
     plain_ms = None
     if not args.no_plain:
@@ -433,7 +464,8 @@ def bench_batched(args, torch, sp, workloads, stream):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "64 systems, n log-uniform [1e3, 2e5], 2D/3D stencil, banded, power-law, "
                                "k in {1,4,8,32} right-hand sides, one graph-captured launch",
-                   "rhs_per_step": nrhs, "union_rows": info["n"], "policy": cand, "waves_per_cu": wpc},
+                   "rhs_per_step": nrhs, "union_rows": info["n"], "policy": cand, "terms_per_lane": tpl,
+                   "waves_per_cu": wpc},
         "roofline": {"bound": "hbm", "achieved": info["bytes_rw"] / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": info["bytes_rw"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None},

@@ -209,6 +209,17 @@ sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, v
 enum { SPTRSV_RHS_AUTO = 0, SPTRSV_RHS_MPASS = 1, SPTRSV_RHS_STAGE = 2 };
 sptrsv_status sptrsv_set_rhs_mode(sptrsv_plan plan, int32_t mode);
 
+/* Row-to-wavefront tiling of the device schedule: within a level, a row of
+ * len terms gets g lanes of a 64-lane tile, g the smallest power of two with
+ * len <= terms_per_lane * g (capped at 64), and a tile holds 64 / g rows of
+ * equal g.  terms_per_lane in {1, 2, 4, 8, 16}; default 4.  Fewer terms per
+ * lane spread a row over more lanes (shorter per-lane chains, fewer rows per
+ * tile); more pack more rows per tile.  Repacks the host image (the upload
+ * becomes stale); the schedule and the rewrite are unchanged.  For tuning the
+ * launch to a matrix (the batched benchmark's autotuner searches it).
+ * Errors: ARG, OVERFLOW, OOM. */
+sptrsv_status sptrsv_set_tiling(sptrsv_plan plan, int32_t terms_per_lane);
+
 /* Value type of the device image: 64 (FP64, the default) or 32.  A plan
  * stored in FP32 keeps every value of L' and M and every diagonal rounded to
  * nearest FP32 and solves in FP32 arithmetic (sptrsv_solve_fp32), with x in

@@ -91,6 +91,7 @@ def load():
         "sptrsv_refine_stats": (S, [P, P, P, P]),
         "sptrsv_set_precision": (S, [P, I32]),
         "sptrsv_set_rhs_mode": (S, [P, I32]),
+        "sptrsv_set_tiling": (S, [P, I32]),
         "sptrsv_solve_stamped": (S, [P, P, P, P, P]),
         "sptrsv_plan_stamp_levels": (S, [P, P]),
         "sptrsv_plan_level_features": (S, [P, P]),
@@ -238,6 +239,12 @@ class Plan:
 
     def set_wait_limit(self, ticks: int):
         _check(load().sptrsv_set_wait_limit(self._h, int(ticks)))
+
+    def set_tiling(self, terms_per_lane: int = 4) -> "Plan":
+        """Row-to-wavefront tiling: terms per lane before a row gets more
+        lanes (1, 2, 4, 8 or 16; repacks)."""
+        _check(load().sptrsv_set_tiling(self._h, int(terms_per_lane)))
+        return self
 
     def set_rhs_mode(self, mode: str = "auto") -> "Plan":
         """How b' = b + M b is applied: 'auto', 'mpass' or 'stage' (repacks)."""

@@ -327,6 +327,27 @@ sptrsv_status sptrsv_set_precision(sptrsv_plan plan, int32_t bits) {
     });
 }
 
+sptrsv_status sptrsv_set_tiling(sptrsv_plan plan, int32_t terms_per_lane) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+        if (terms_per_lane < 1 || terms_per_lane > 16 || (terms_per_lane & (terms_per_lane - 1)))
+            return set_err(SPTRSV_ERR_ARG, "terms_per_lane must be 1, 2, 4, 8 or 16");
+        if (terms_per_lane == plan->terms_per_lane) return SPTRSV_OK;
+        const int old = plan->terms_per_lane;
+        plan->terms_per_lane = terms_per_lane;
+        plan->uploaded = false;
+        drop_graph(*plan);
+        try {
+            sptrsv::pack(*plan);
+        } catch (...) {
+            plan->terms_per_lane = old;
+            sptrsv::pack(*plan);
+            throw;
+        }
+        return SPTRSV_OK;
+    });
+}
+
 sptrsv_status sptrsv_set_rhs_mode(sptrsv_plan plan, int32_t mode) {
     return guarded([&]() -> sptrsv_status {
         if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");

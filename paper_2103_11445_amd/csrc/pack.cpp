@@ -11,7 +11,8 @@
 //
 // Wide items.  Within a level, rows are binned by term count (b-terms +
 // x-terms): a row of `len` terms gets g lanes, the smallest power of two with
-// len <= kTermsPerLane * g (capped at 64).  A tile holds 64/g rows of one bin
+// len <= t * g (capped at 64), t the plan's terms per lane (4 by default,
+// sptrsv_set_tiling).  A tile holds 64/g rows of one bin
 // of one level; its terms occupy `nchunks` chunks of 64 slots, the t-th term
 // of the tile's r-th row at chunk t / g, lane r * g + t % g.  A term is an
 // x-term (column k, coefficient -L'_ik); unused slots hold INT32_MIN.
@@ -39,15 +40,15 @@
 namespace sptrsv {
 
 namespace {
-constexpr int kTermsPerLane = 4;
+
 constexpr int kBins = 7;  // g = 1, 2, 4, ..., 64
 constexpr int32_t kPad = INT32_MIN;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int bin_of(int64_t len) {
+int bin_of(int64_t len, int terms_per_lane) {
     int lg = 0;
-    while (lg < kBins - 1 && len > (int64_t)kTermsPerLane << lg) ++lg;
+    while (lg < kBins - 1 && len > (int64_t)terms_per_lane << lg) ++lg;
     return lg;
 }
 
@@ -106,6 +107,7 @@ void pack(Plan &p) {
             std::unique_ptr<Plan> sub(new Plan());
             sub->is_sub = true;
             sub->precision = p.precision;
+            sub->terms_per_lane = p.terms_per_lane;
             analyse(*sub, n, brp.data(), bci.data(), bval.data());
             sub->upper = p.upper;
             sptrsv_policy none{};
@@ -182,7 +184,7 @@ void pack(Plan &p) {
             continue;
         }
         int32_t cnt[kBins] = {0};
-        for (int32_t q = b0; q < b1; ++q) ++cnt[bin_of(len[(size_t)p.sched_rows[(size_t)q]])];
+        for (int32_t q = b0; q < b1; ++q) ++cnt[bin_of(len[(size_t)p.sched_rows[(size_t)q]], p.terms_per_lane)];
         int32_t start[kBins];
         int32_t acc = slot;
         for (int g = 0; g < kBins; ++g) {
@@ -193,7 +195,7 @@ void pack(Plan &p) {
         std::copy(start, start + kBins, cur);
         for (int32_t q = b0; q < b1; ++q) {
             const int32_t r = p.sched_rows[(size_t)q];
-            slot_row[(size_t)cur[bin_of(len[(size_t)r])]++] = r;
+            slot_row[(size_t)cur[bin_of(len[(size_t)r], p.terms_per_lane)]++] = r;
         }
         for (int g = 0; g < kBins; ++g) {
             const int32_t per = 64 >> g;
@@ -231,7 +233,7 @@ void pack(Plan &p) {
         int32_t cnt[kBins] = {0};
         auto mlen = [&](int32_t i) { return p.m_ptr[(size_t)i + 1] - p.m_ptr[(size_t)i]; };
         auto row_at = [&](int32_t d) { return p.upper ? n - 1 - d : d; };  // plan row of caller index d
-        for (int32_t i = 0; i < n; ++i) ++cnt[bin_of(mlen(i))];
+        for (int32_t i = 0; i < n; ++i) ++cnt[bin_of(mlen(i), p.terms_per_lane)];
         int32_t start[kBins], cur[kBins], acc = 0;
         for (int g = 0; g < kBins; ++g) {
             start[g] = cur[g] = acc;
@@ -239,7 +241,7 @@ void pack(Plan &p) {
         }
         for (int32_t d = 0; d < n; ++d) {
             const int32_t r = row_at(d);
-            mslot_row[(size_t)cur[bin_of(mlen(r))]++] = r;
+            mslot_row[(size_t)cur[bin_of(mlen(r), p.terms_per_lane)]++] = r;
         }
         for (int g = 0; g < kBins; ++g) {
             const int32_t per = 64 >> g;

@@ -113,6 +113,9 @@ struct Plan {
     // right-hand-side step: requested (-1 = chosen from the sizes of M and
     // L_B) and, for kRhsStage, the plan of the stage system L_B
     int32_t rhs_request = -1;
+    // row-to-wavefront tiling: a row of len terms gets the smallest power of
+    // two g of lanes with len <= terms_per_lane * g (capped at 64)
+    int terms_per_lane = 4;
     std::unique_ptr<struct Plan> sub;
     bool is_sub = false;  // a stage system (no residual data, no sub-plan)
     std::vector<int32_t> rp, ci;

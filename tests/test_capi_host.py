@@ -464,3 +464,21 @@ def test_rhs_modes(sp):
     # the mode survives a rewrite, and FP32 packing carries the stage system too
     plan.set_precision(32).rewrite("threshold", max_width=INF, max_depth=8, max_fill=12.0)
     assert plan.info()["rhs_mode"] == 2
+
+
+def test_tiling_knob(sp):
+    """Terms per lane change the tile shapes only: more terms per lane pack
+    more rows per tile (fewer tiles); the rewritten system is unchanged."""
+    s = wl.powerlaw(50000, 2000, seed=1)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", max_width=INF, max_depth=4, max_fill=10.0)
+    lp0, m0 = plan.export()
+    tiles = []
+    for t in (1, 2, 4, 8, 16):
+        plan.set_tiling(t)
+        tiles.append(plan.info()["tiles"])
+    assert tiles == sorted(tiles, reverse=True) and tiles[0] > tiles[-1]
+    for a, b in zip(plan.export()[0] + plan.export()[1], lp0 + m0):
+        assert np.array_equal(a, b)
+    lib = sp.load()
+    for bad in (0, 3, 32, -4):
+        assert sp.STATUS[lib.sptrsv_set_tiling(plan._h, bad)] == "ERR_ARG"

@@ -111,3 +111,24 @@ def test_stage_mode_timeout_reported(torch, sp):
     x = plan.solve(b)
     assert plan.check() == 0
     assert errors(x.cpu().numpy(), oracle.solve(s.row_ptr, s.col_idx, s.val, s.b))[1] <= TOL
+
+
+@pytest.mark.parametrize("tpl", [1, 2, 8, 16])
+@pytest.mark.parametrize("make", [
+    lambda: wl.stencil3d(24, seed=61),
+    lambda: wl.banded(20011, 200, 8, 24, seed=62),
+    lambda: wl.powerlaw(100003, 1501, seed=63),
+    lambda: wl.random_lower(700, 0.6, seed=64),
+])
+def test_tilings_match_oracle(torch, sp, make, tpl):
+    """Every row-to-wavefront tiling solves to the gate (rows over 1..64
+    lanes, up to 16 chunks a row)."""
+    s = make()
+    ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", max_width=INF, max_depth=8, max_fill=12.0)
+    plan.set_tiling(tpl).upload()
+    x = plan.solve(torch.from_numpy(s.b).cuda())
+    assert plan.check() == 0
+    err = errors(x.cpu().numpy(), ref)
+    print(s.name, tpl, plan.info()["tiles"], err, flush=True)
+    assert err[1] <= TOL
