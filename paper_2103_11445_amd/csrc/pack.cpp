@@ -1,16 +1,17 @@
 // pack.cpp -- device image of a plan: the executed schedule (level sets of
-// L') as a list of work items in level order, and the right-hand-side
-// combination b' = b + M b as a separate set of tiles.
+// L') as a list of work items in level order, and what the right-hand-side
+// step b' = b + M b needs.
 //
 // Right-hand side.  The b-terms of the rewritten rows depend on nothing the
-// solve computes, so they are not part of the schedule: a fully parallel
-// pass over "M tiles" (rows binned by their count of b-terms, the same tile
-// shape as below) computes b'_i = b_i + sum_j M_ij b_j for every row (and
-// resets x) before the dependent solve starts.  The solve tiles hold x-terms
-// only and read b'_i.
+// solve computes, so they are not part of the schedule.  Either a fully
+// parallel pass over "M tiles" (rows binned by their count of b-terms, the
+// same tile shape as below) computes b'_i = b_i + sum_j M_ij b_j for every
+// row (and resets x), or, when M is large, the image carries a second plan:
+// the stages' diagonal blocks of L (L_B), whose solve y gives b' = D y.  The
+// solve tiles hold x-terms only and read b' (or y, scaled by the diagonal).
 //
-// Wide items.  Within a level, rows are binned by term count (b-terms +
-// x-terms): a row of `len` terms gets g lanes, the smallest power of two with
+// Wide items.  Within a level, rows are binned by x-term count: a row of
+// `len` terms gets g lanes, the smallest power of two with
 // len <= t * g (capped at 64), t the plan's terms per lane (4 by default,
 // sptrsv_set_tiling).  A tile holds 64/g rows of one bin
 // of one level; its terms occupy `nchunks` chunks of 64 slots, the t-th term

@@ -15,15 +15,15 @@
 //     is gone; the producer publishes x_i with one device-scope 8-byte store.
 //     Device (agent) scope keeps the eight XCDs' L2 caches out of the way.
 //   * Latency hiding in wide tiles: a wave issues every gather of its current
-//     tile at once (x polls, b-terms, b_i), then the loads of its next tile's
-//     terms, and only then waits for the gathers; the next descriptor is
-//     fetched two items ahead.
+//     tile at once (x-terms and the row's constant), then the loads of its
+//     next tile's terms, and only then waits for the gathers; the next
+//     descriptor is fetched two items ahead.
 //   * Segments (runs of narrow levels, e.g. a long serial chain) are one
 //     work item executed by one wave tile after tile.  Rows the segment
 //     produced recently are read from the wave's LDS ring instead of global
 //     memory, and the wave runs a software pipeline: term loads kDepth tiles
-//     ahead, b / external-x gathers kDepth/2 tiles ahead, so the critical
-//     path waits only on LDS and on loads issued several tiles before.
+//     ahead, constant / external-x gathers kDepth/2 tiles ahead, so the
+//     critical path waits only on LDS and on loads issued several tiles before.
 //   * The rewritten right-hand side b' = b + M b depends on nothing the
 //     solve computes, so the solve's tiles hold x-terms only and b' comes
 //     from a step before it: either a fully parallel pass over M (prepare),
