@@ -62,6 +62,7 @@ CANDIDATES = {
 TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth256", "powerlaw_4m": "paper256",
          "stencil2d_100": "paper"}
 TUNED_TILING = {"stencil3d_128": 4, "banded_1m": 4, "powerlaw_4m": 2, "stencil2d_100": 4}
+TUNED_WAVES = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
 
 
 def log(*a):
@@ -79,7 +80,8 @@ def kernel_sources_hash() -> str:
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2103_11445_amd", "libsptrsv.so"), "rb") as fh:
         h.update(fh.read())
-    h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n]] for n in LARGE}, sort_keys=True).encode())
+    h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n], TUNED_WAVES[n]] for n in LARGE},
+                        sort_keys=True).encode())
     return h.hexdigest()
 
 
@@ -118,8 +120,8 @@ def main():
                     help="only run 5 device-to-device copies of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solve is not sharded across GPUs (DESIGN.md, "
-              "'How it would shard'); run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the solve is not sharded across GPUs; "
+              "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -204,16 +206,18 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     # ---- tuning leg
-    plans, chosen, tuning, tiling = {}, {}, {}, {}
+    plans, chosen, tuning, tiling, waves = {}, {}, {}, {}, {}
     for n in names:
         if args.no_tune:
             chosen[n] = TUNED.get(n, "paper")
             tiling[n] = TUNED_TILING.get(n, 4)
+            waves[n] = TUNED_WAVES.get(n, 0)
             plans[n], h = make_plan(n, chosen[n])
             if tiling[n] != 4:
                 plans[n].set_tiling(tiling[n])
                 plans[n]._buf = None
                 plans[n].upload()
+            plans[n].set_launch(waves[n])
             host[n].update(h)
             continue
         best = None
@@ -251,6 +255,19 @@ def main():
         plans[n].set_tiling(tiling[n])
         plans[n]._buf = None
         plans[n].upload()
+        # waves per CU of the cooperative launch (0 = chosen from the plan)
+        waves[n] = 0
+        best_ms = time_solves(plans[n], n, 2)
+        for wpc in (2, 4, 8):
+            plans[n].set_launch(wpc)
+            ms = time_solves(plans[n], n, 2)
+            tuning[n][f"{chosen[n]}/t{tiling[n]}/wpc{wpc}"] = {"ms": ms, "levels_rw": plans[n].info()["levels_rw"],
+                                                               "entries": tuning[n][chosen[n]]["entries"],
+                                                               "status": plans[n].check()}
+            log(f"[tune] {n} {chosen[n]} terms/lane {tiling[n]} waves/CU {wpc}: {ms:.3f} ms")
+            if ms < 0.97 * best_ms:
+                best_ms, waves[n] = ms, wpc
+        plans[n].set_launch(waves[n])
 
     # ---- timed leg
     def run(plan_set, steps, tag):
@@ -299,6 +316,7 @@ def main():
             "levels_rw": i["levels_rw"], "entries_rw": i["nnz_rw"] + i["nnz_m"],
             "flops": i["flops"], "flops_rw": i["flops_rw"], "bytes": i["bytes"],
             "bytes_rw": i["bytes_rw"], "policy": chosen[n], "terms_per_lane": tiling[n],
+            "waves_per_cu": waves[n],
             "rhs_mode": i["rhs_mode"], "ms_per_solve": per[n],
             "solves_per_s": 1000.0 / per[n],
             "plan_gbps": i["bytes_rw"] / (per[n] * 1e-3) / 1e9,
@@ -331,7 +349,8 @@ def main():
     # measured HBM bytes (rocprofv3 counters, calibrated) of the same kernel,
     # plans and workload; only valid for the tuned policies it was taken with
     traffic = None
-    if args.workload == "large" and all(chosen[n] == TUNED[n] and tiling[n] == TUNED_TILING[n] for n in names):
+    if args.workload == "large" and all(chosen[n] == TUNED[n] and tiling[n] == TUNED_TILING[n]
+                                        and waves[n] == TUNED_WAVES[n] for n in names):
         traffic = profiled_traffic()
     if traffic is not None:
         for n in names:
