@@ -57,11 +57,16 @@ CANDIDATES = {
     "depth64": ("threshold", {"max_width": INF, "max_depth": 64, "max_fill": 40.0}),
     "depth128": ("threshold", {"max_width": INF, "max_depth": 128, "max_fill": 48.0}),
     "depth256": ("threshold", {"max_width": INF, "max_depth": 256, "max_fill": 72.0}),
+    # tried only when the next shallower one wins (see DEEPER): the host-side
+    # rewrite grows with the stage depth (the banded matrix at 512 levels:
+    # ~30 s and ~25 GB of host memory for M)
+    "depth512": ("threshold", {"max_width": INF, "max_depth": 512, "max_fill": 140.0}),
 }
+DEEPER = {"depth256": "depth512"}
 # Result of the tuning leg on MI355X (used by --no-tune, e.g. under a profiler).
-TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth256", "powerlaw_4m": "paper256",
+TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth512", "powerlaw_4m": "paper256",
          "stencil2d_100": "paper"}
-TUNED_TILING = {"stencil3d_128": 4, "banded_1m": 4, "powerlaw_4m": 2, "stencil2d_100": 4}
+TUNED_TILING = {"stencil3d_128": 4, "banded_1m": 8, "powerlaw_4m": 2, "stencil2d_100": 4}
 TUNED_WAVES = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
 
 
@@ -222,7 +227,9 @@ def main():
             continue
         best = None
         tuning[n] = {}
-        for cand in CANDIDATES:
+        queue = [c for c in CANDIDATES if c not in DEEPER.values()]
+        while queue:
+            cand = queue.pop(0)
             p, h = make_plan(n, cand)
             ms = time_solves(p, n, 2)
             st = p.check()
@@ -237,6 +244,8 @@ def main():
                 best = (ms, p, cand, h)
             else:
                 p.close()
+            if not queue and best[2] in DEEPER and DEEPER[best[2]] not in tuning[n]:
+                queue.append(DEEPER[best[2]])
         _, plans[n], chosen[n], h = best
         host[n].update(h)
         # row-to-wavefront tiling of the chosen plan

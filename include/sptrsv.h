@@ -158,7 +158,8 @@ sptrsv_status sptrsv_analyse_batch(int32_t count, const int32_t *n, const int32_
  * combination M (b'_i = b_i + sum_j M_ij b_j), re-levels L' (emptied levels
  * vanish) and packs the device image.  Host only; invalidates a previous
  * upload.  Errors: ARG (bad policy), OVERFLOW (the device image would need
- * more than INT32_MAX 64-lane chunks or entries), OOM. */
+ * more than INT32_MAX 64-lane chunks or entries, or n times the value size
+ * reaches 2^32 bytes: the kernels address x and b by 32-bit offsets), OOM. */
 sptrsv_status sptrsv_rewrite(sptrsv_plan plan, const sptrsv_policy *policy);
 
 /* Size in bytes of the device buffer the current plan needs (image plus
@@ -201,7 +202,10 @@ sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, v
  *                     b' = D y with L_B y = b, L_B the block-diagonal part of
  *                     L inside the stages: one more solve, by the same kernel,
  *                     whose chain is one stage deep (the stages are
- *                     independent) and which reads nnz(L_B) <= nnz(L) entries.
+ *                     independent) and which reads nnz(L_B) <= nnz(L) entries;
+ *                     a stage of at most a few segment tiles per level is
+ *                     solved start to finish by one wave (its values kept in
+ *                     LDS), the others level by level across the grid.
  *   SPTRSV_RHS_AUTO   (default) the stage solve when nnz(M) > 2 nnz(L_B).
  * The results agree up to rounding.  Repacks the host image (the upload
  * becomes stale); the rewrite and its introspection are unchanged.
@@ -271,7 +275,8 @@ sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu);
 /* Upper bound, in ticks of the 100 MHz GPU real-time clock, on a single
  * dependency wait (default 200,000,000 = 2 s).  A wait that reaches it
  * gives up, marks the plan's status word and lets the kernel drain.
- * For tests of the failure path.  Takes effect at the next solve. */
+ * For tests of the failure path.  Takes effect at the next solve.
+ * Errors: ARG (plan NULL). */
 sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks);
 
 /* Plan statistics (Sec. V reports levels and FLOPs before and after).
@@ -303,6 +308,9 @@ typedef struct {
     int32_t rhs_mode;    /* right-hand-side step in use: 0 none (no b-terms),
                             SPTRSV_RHS_MPASS or SPTRSV_RHS_STAGE */
     int64_t nnz_rhs;     /* entries it reads: nnz(M), or nnz(L_B) */
+    int32_t rhs_segments;/* stage solve: stages solved whole by one wave each
+                            (no wait on another wave); the others run level
+                            by level across the grid */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

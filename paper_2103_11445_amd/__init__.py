@@ -56,7 +56,8 @@ class _Info(ctypes.Structure):
                 ("bytes", ctypes.c_int64), ("bytes_rw", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("seg_tiles", ctypes.c_int64),
-                ("rhs_mode", ctypes.c_int32), ("nnz_rhs", ctypes.c_int64)]
+                ("rhs_mode", ctypes.c_int32), ("nnz_rhs", ctypes.c_int64),
+                ("rhs_segments", ctypes.c_int32)]
 
 
 _lib = None

@@ -66,6 +66,9 @@ int launch_waves(const sptrsv::Plan &p) {
         const double want = 2.0 * per_level / std::max(1, p.cus);
         wpc = 1;
         while (wpc < 8 && wpc * 2 <= want) wpc *= 2;
+        // a stage system's whole-stage segments each on a wave of their own
+        if (p.comp_segs > 0)
+            wpc = std::max<int>(wpc, (int)((p.comp_segs + std::max(1, p.cus) - 1) / std::max(1, p.cus)));
     }
     wpc = std::min(wpc, p.max_waves_per_cu);
     const int64_t w = std::min<int64_t>((int64_t)p.cus * wpc, p.ntiles);
@@ -472,6 +475,7 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->tiles = p.ntiles;
     o->precision = p.precision;
     o->seg_tiles = p.nseg_tiles;
+    o->rhs_segments = p.sub ? p.sub->comp_segs : 0;
     return SPTRSV_OK;
 }
 

@@ -95,6 +95,9 @@ void pack(Plan &p) {
     const int32_t n = p.n;
     if ((int64_t)n + kRing > INT32_MAX)
         throw Error{SPTRSV_ERR_OVERFLOW, "n too large for the device encoding"};
+    // the kernels address x and b by 32-bit byte offsets
+    if ((uint64_t)n * (uint64_t)(p.precision / 8) > 0xFFFFFFFFull)
+        throw Error{SPTRSV_ERR_OVERFLOW, "n * value bytes beyond 2^32 (32-bit gather offsets)"};
     // ---- right-hand-side step
     int32_t rhs_mode = kRhsNone;
     int64_t nnz_rhs = 0;
@@ -111,6 +114,8 @@ void pack(Plan &p) {
             sub->terms_per_lane = p.terms_per_lane;
             analyse(*sub, n, brp.data(), bci.data(), bval.data());
             sub->upper = p.upper;
+            sub->comp.resize((size_t)n);
+            for (int32_t i = 0; i < n; ++i) sub->comp[(size_t)i] = p.stage_of_level[(size_t)p.level[(size_t)i]];
             sptrsv_policy none{};
             none.kind = SPTRSV_POLICY_NONE;
             rewrite(*sub, none);  // packs the stage system's image
@@ -153,39 +158,13 @@ void pack(Plan &p) {
     std::vector<SegTile> stiles;
     std::vector<Item> items;
     std::vector<int32_t> seg_of_slot((size_t)n, -1);   // segment id of each slot
-    std::vector<int32_t> seg_tile_first;                // first slot of each segment tile
     int64_t nchunks = 0;
     int32_t slot = 0, nseg = 0;
-    for (int32_t l = 0; l < L; ++l) {
-        const int32_t b0 = p.sched_ptr[(size_t)l], b1 = p.sched_ptr[(size_t)l + 1];
-        if (in_seg[(size_t)l]) {
-            if (l == 0 || !in_seg[(size_t)l - 1]) {
-                items.push_back({1, (int64_t)stiles.size(), 0, -1});
-                ++nseg;
-            }
-            const int lg = seg_lg[(size_t)l];
-            const int32_t per = 64 >> lg;
-            for (int32_t q = b0; q < b1; ++q) {
-                slot_row[(size_t)(slot + q - b0)] = p.sched_rows[(size_t)q];
-                seg_of_slot[(size_t)(slot + q - b0)] = nseg - 1;
-            }
-            for (int32_t s = slot; s < slot + (b1 - b0); s += per) {
-                stiles.push_back({s, std::min(per, slot + (b1 - b0) - s), lg, l});
-                items.back().b += 1;
-            }
-            slot += b1 - b0;
-            if (l + 1 == L || !in_seg[(size_t)l + 1]) {
-                // pad the segment to a whole number of pipeline steps with
-                // empty tiles (no rows, no terms)
-                while (items.back().b % kSegDepth) {
-                    stiles.push_back({slot, 0, 0, -1});
-                    items.back().b += 1;
-                }
-            }
-            continue;
-        }
+
+    // rows[0, count) of level l (ascending) as wide tiles, binned by length
+    auto wide_level = [&](const int32_t *rows, int32_t count, int32_t l) {
         int32_t cnt[kBins] = {0};
-        for (int32_t q = b0; q < b1; ++q) ++cnt[bin_of(len[(size_t)p.sched_rows[(size_t)q]], p.terms_per_lane)];
+        for (int32_t q = 0; q < count; ++q) ++cnt[bin_of(len[(size_t)rows[q]], p.terms_per_lane)];
         int32_t start[kBins];
         int32_t acc = slot;
         for (int g = 0; g < kBins; ++g) {
@@ -194,8 +173,8 @@ void pack(Plan &p) {
         }
         int32_t cur[kBins];
         std::copy(start, start + kBins, cur);
-        for (int32_t q = b0; q < b1; ++q) {
-            const int32_t r = p.sched_rows[(size_t)q];
+        for (int32_t q = 0; q < count; ++q) {
+            const int32_t r = rows[q];
             slot_row[(size_t)cur[bin_of(len[(size_t)r], p.terms_per_lane)]++] = r;
         }
         for (int g = 0; g < kBins; ++g) {
@@ -211,6 +190,118 @@ void pack(Plan &p) {
             }
         }
         slot = acc;
+    };
+    // a new segment
+    auto open_segment = [&]() {
+        items.push_back({1, (int64_t)stiles.size(), 0, -1});
+        ++nseg;
+    };
+    // rows[0, count) of level l appended to the open segment as tiles of
+    // 2^lg lanes per row; `level` is what their stamps report
+    auto seg_level = [&](const int32_t *rows, int32_t count, int lg, int32_t level) {
+        const int32_t per = 64 >> lg;
+        for (int32_t q = 0; q < count; ++q) {
+            slot_row[(size_t)(slot + q)] = rows[q];
+            seg_of_slot[(size_t)(slot + q)] = nseg - 1;
+        }
+        for (int32_t s = slot; s < slot + count; s += per) {
+            stiles.push_back({s, std::min(per, slot + count - s), lg, level});
+            items.back().b += 1;
+        }
+        slot += count;
+    };
+    // pad the open segment to a whole number of pipeline steps with empty
+    // tiles (no rows, no terms)
+    auto close_segment = [&]() {
+        while (items.back().b % kSegDepth) {
+            stiles.push_back({slot, 0, 0, -1});
+            items.back().b += 1;
+        }
+    };
+
+    // ---- independent stages of a stage system: a stage whose levels need
+    // at most kStageSegTiles segment tiles each (on average) runs as one
+    // segment, start to finish on one wave, with no wait on another wave;
+    // the remaining rows follow as wide tiles, level by level
+    std::vector<int32_t> comp_rows, comp_ptr;  // rows of each stage in schedule order
+    std::vector<char> comp_seg;
+    int32_t ncomp = 0, comp_segs = 0;
+    if (!p.comp.empty()) {
+        for (int32_t i = 0; i < n; ++i) ncomp = std::max(ncomp, p.comp[(size_t)i] + 1);
+        comp_ptr.assign((size_t)ncomp + 1, 0);
+        for (int32_t i = 0; i < n; ++i) ++comp_ptr[(size_t)p.comp[(size_t)i] + 1];
+        for (int32_t c = 0; c < ncomp; ++c) comp_ptr[(size_t)c + 1] += comp_ptr[(size_t)c];
+        comp_rows.resize((size_t)n);
+        std::vector<int32_t> fill(comp_ptr.begin(), comp_ptr.end() - 1);
+        for (int32_t q = 0; q < n; ++q) {
+            const int32_t r = p.sched_rows[(size_t)q];
+            comp_rows[(size_t)fill[(size_t)p.comp[(size_t)r]]++] = r;
+        }
+        comp_seg.assign((size_t)ncomp, 0);
+        std::vector<int64_t> ctiles((size_t)ncomp, 0);
+        for (int32_t c = 0; c < ncomp; ++c) {
+            int64_t depth = 0, ntl = 0;
+            bool ok = true;
+            for (int32_t q = comp_ptr[(size_t)c]; q < comp_ptr[(size_t)c + 1] && ok;) {
+                const int32_t l = p.level_rw[(size_t)comp_rows[(size_t)q]];
+                int32_t e = q;
+                int64_t mx = 0;
+                for (; e < comp_ptr[(size_t)c + 1] && p.level_rw[(size_t)comp_rows[(size_t)e]] == l; ++e)
+                    mx = std::max(mx, len[(size_t)comp_rows[(size_t)e]]);
+                const int lg = seg_lanes_log2(mx);
+                ok = lg >= 0;
+                if (ok) ntl += (e - q + (64 >> lg) - 1) / (64 >> lg);
+                ++depth;
+                q = e;
+            }
+            comp_seg[(size_t)c] = ok && depth >= 2 && ntl <= (int64_t)kStageSegTiles * depth;
+            ctiles[(size_t)c] = ntl;
+            comp_segs += comp_seg[(size_t)c];
+        }
+        if (comp_segs == 0) {
+            comp_rows.clear();
+        } else {
+            // longest first, so that a wave holding two of them gets short ones
+            std::vector<int32_t> order;
+            for (int32_t c = 0; c < ncomp; ++c)
+                if (comp_seg[(size_t)c]) order.push_back(c);
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t u, int32_t v) { return ctiles[(size_t)u] > ctiles[(size_t)v]; });
+            for (int32_t c : order) {
+                open_segment();
+                for (int32_t q = comp_ptr[(size_t)c]; q < comp_ptr[(size_t)c + 1];) {
+                    const int32_t l = p.level_rw[(size_t)comp_rows[(size_t)q]];
+                    int32_t e = q;
+                    int64_t mx = 0;
+                    for (; e < comp_ptr[(size_t)c + 1] && p.level_rw[(size_t)comp_rows[(size_t)e]] == l; ++e)
+                        mx = std::max(mx, len[(size_t)comp_rows[(size_t)e]]);
+                    seg_level(comp_rows.data() + q, e - q, seg_lanes_log2(mx), -1);
+                    q = e;
+                }
+                close_segment();
+            }
+            std::vector<int32_t> rest;
+            for (int32_t l = 0; l < L; ++l) {
+                rest.clear();
+                for (int32_t q = p.sched_ptr[(size_t)l]; q < p.sched_ptr[(size_t)l + 1]; ++q) {
+                    const int32_t r = p.sched_rows[(size_t)q];
+                    if (!comp_seg[(size_t)p.comp[(size_t)r]]) rest.push_back(r);
+                }
+                if (!rest.empty()) wide_level(rest.data(), (int32_t)rest.size(), l);
+            }
+        }
+    }
+    if (comp_segs == 0) {
+        for (int32_t l = 0; l < L; ++l) {
+            const int32_t b0 = p.sched_ptr[(size_t)l], b1 = p.sched_ptr[(size_t)l + 1];
+            if (!in_seg[(size_t)l]) {
+                wide_level(p.sched_rows.data() + b0, b1 - b0, l);
+                continue;
+            }
+            if (l == 0 || !in_seg[(size_t)l - 1]) open_segment();
+            seg_level(p.sched_rows.data() + b0, b1 - b0, seg_lg[(size_t)l], l);
+            if (l + 1 == L || !in_seg[(size_t)l + 1]) close_segment();
+        }
     }
     if (nchunks > INT32_MAX || (int64_t)items.size() > INT32_MAX || (int64_t)stiles.size() * 64 > INT32_MAX)
         throw Error{SPTRSV_ERR_OVERFLOW, "device image needs more than INT32_MAX chunks"};
@@ -483,6 +574,7 @@ void pack(Plan &p) {
     p.nchunks = nchunks;
     p.nseg = nseg;
     p.nseg_tiles = nst;
+    p.comp_segs = comp_segs;
     p.uploaded = false;
 }
 

@@ -23,7 +23,9 @@ constexpr int kSegChunks = 4;     // chunks per segment tile
 constexpr int kRing = 2048;       // x values a segment wave keeps in LDS (power of two)
 constexpr int kNarrowTiles = 2;   // a level of at most this many segment tiles is narrow
 constexpr int kMinSegLevels = 16; // shortest run of narrow levels executed as a segment
-constexpr int kSegDepth = 4;      // segment software-pipeline depth; segments hold a multiple of it
+constexpr int kSegDepth = 8;      // segment software-pipeline depth; segments hold a multiple of it
+constexpr int kStageSegTiles = 4; // a stage of a stage system is one segment if it needs at most this
+                                  // many segment tiles per level
 
 constexpr int kMaxRefine = 16;    // refinement iterations per call (slots in the workspace)
 
@@ -118,6 +120,9 @@ struct Plan {
     int terms_per_lane = 4;
     std::unique_ptr<struct Plan> sub;
     bool is_sub = false;  // a stage system (no residual data, no sub-plan)
+    // a stage system's stage of each row: its diagonal blocks are
+    // independent systems, and a narrow one is packed as one segment
+    std::vector<int32_t> comp;
     std::vector<int32_t> rp, ci;
     std::vector<double> val;
     std::vector<int32_t> level;  // level of each row of L
@@ -143,6 +148,7 @@ struct Plan {
     int64_t nchunks = 0;
     int32_t nseg = 0;        // segments
     int64_t nseg_tiles = 0;  // tiles inside segments
+    int32_t comp_segs = 0;   // segments that are whole independent stages
     // executed level (of L') whose rows each item and each segment tile
     // finish, -1 for segment items and padding tiles: the map of the
     // completion stamps of an instrumented solve

@@ -115,17 +115,6 @@ __device__ inline typename Val<T>::Bits load_agent(const T *p) {
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// First attempt at a gather: an ordinary (cached) load.  Stream order makes
-// the fill of x visible to this kernel and no cache holds x lines from before
-// it, so within the solve a cached copy of x_k is either the not-ready
-// pattern or the final value: a stale pattern only sends the lane to the
-// device-scope poll, never yields a wrong value.  It lets repeated gathers
-// of a published value hit in L2 instead of going to memory each time.
-template <typename T>
-__device__ inline typename Val<T>::Bits load_cached(const T *p) {
-    return *reinterpret_cast<const typename Val<T>::Bits *>(p);
-}
-
 // Bits of x[k] once it is published (a quiet NaN if the wait gave up).
 // Only reached behind a wave-uniform branch (see resolve_pending), so the
 // call and the waits it implies stay off the path where nothing is pending.
@@ -148,11 +137,26 @@ __device__ __noinline__ typename Val<T>::Bits wait_slow(const T *x, int32_t k, s
     }
 }
 
-// Address a term gathers from: x_k for x-terms (0 <= k < n), the dummy b'_0
-// for pads and LDS-ring terms (k >= n, read from the ring instead).
+// Element k of a (uniform) array as a 32-bit byte offset from its base, so
+// that the load takes the scalar-base form (no 64-bit address per lane; the
+// packer keeps n * sizeof(T) below 2^32).
 template <typename T>
-__device__ inline const T *gather_addr(const SolveArgs<T> &a, int32_t k) {
-    return k >= 0 && k < a.n ? a.x + k : a.b;
+__device__ inline typename Val<T>::Bits load_at(const T *base, int32_t k) {
+    const uint32_t off = (uint32_t)k * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const typename Val<T>::Bits *>(reinterpret_cast<const char *>(base) + off);
+}
+
+// First attempt at a term's gather, an ordinary (cached) load: x_k for
+// x-terms (0 <= k < n); x_0 for pads and LDS-ring terms (k outside [0, n)),
+// whose value is not used.  Stream order makes the fill of x visible to this
+// kernel and no cache holds x lines from before it, so within the solve a
+// cached copy of x_k is either the not-ready pattern or the final value: a
+// stale pattern only sends the lane to the device-scope poll, never yields a
+// wrong value.  It lets repeated gathers of a published value hit in L2
+// instead of going to memory each time.
+template <typename T>
+__device__ inline typename Val<T>::Bits gather_x(const SolveArgs<T> &a, int32_t k) {
+    return load_at(a.x, k >= 0 && k < a.n ? k : 0);
 }
 
 template <typename T>
@@ -411,9 +415,8 @@ __device__ inline void seg_load(const SolveArgs<T> &a, long long st, int lane, S
 template <typename T>
 __device__ inline void seg_gather(const SolveArgs<T> &a, SegSlot<T> &S) {
 #pragma unroll
-    for (int c = 0; c < kSegChunks; ++c) S.g[c] = load_cached(gather_addr(a, seg_col(S, c)));
-    S.bi = a.b[S.rm.x >= 0 ? S.rm.x : 0];
-    if (a.bscale) S.bi *= S.diag;
+    for (int c = 0; c < kSegChunks; ++c) S.g[c] = gather_x(a, seg_col(S, c));
+    S.bi = Val<T>::of(load_at(a.b, S.rm.x >= 0 ? S.rm.x : 0));
 }
 
 template <typename T>
@@ -421,17 +424,25 @@ __device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring)
     int32_t col[kSegChunks];
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) col[c] = seg_col(S, c);
+    // every chunk reads the ring (terms that are not ring terms read some
+    // slot and discard it): the reads go out together, with one wait,
+    // instead of one branch and one wait per chunk
+    T rv[kSegChunks];
+#pragma unroll
+    for (int c = 0; c < kSegChunks; ++c) rv[c] = ring[((uint32_t)col[c] - (uint32_t)a.n) & (kRing - 1)];
     resolve_pending<kSegChunks, false>(a, col, S.g);
     T acc = T(0);
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) {
         const int32_t k = col[c];
-        const T v = k >= a.n ? ring[k - a.n] : term_value<T>(k, S.g[c]);
+        const T v = k >= a.n ? rv[c] : term_value<T>(k, S.g[c]);
         acc = fma(seg_val(S, c), v, acc);
     }
     acc = group_sum(acc, __builtin_amdgcn_readfirstlane(S.rm.y) & 0xff);
     if (S.rm.x >= 0) {
-        const T xi = (S.bi + acc) / S.diag;
+        // scaled here, not at the gather, so the pipeline never waits on it
+        const T bi = a.bscale ? S.bi * S.diag : S.bi;
+        const T xi = (bi + acc) / S.diag;
         ring[S.rm.y >> 8] = xi;
         __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + S.rm.x, Val<T>::bits(xi),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -509,10 +520,10 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < kRegChunks; ++c) {
             col[c] = tile_col(cur, c, lane);
-            g[c] = load_cached(gather_addr(a, col[c]));
+            g[c] = gather_x(a, col[c]);
         }
         const bool lead = tile_lead(cur.d, lane);
-        const T braw = a.b[lead ? cur.row : 0];
+        const T braw = Val<T>::of(load_at(a.b, lead ? cur.row : 0));
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         // 2. the next tile's terms and the descriptor after it
@@ -546,7 +557,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
 #pragma unroll
             for (int u = 0; u < kRegChunks; ++u) {
                 if (!act || c0 + u >= cur.d.z) kc[u] = kPad;
-                gc[u] = load_cached(gather_addr(a, kc[u]));
+                gc[u] = gather_x(a, kc[u]);
             }
             resolve_pending<kRegChunks, true>(a, kc, gc);
 #pragma unroll

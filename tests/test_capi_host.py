@@ -466,6 +466,53 @@ def test_rhs_modes(sp):
     assert plan.info()["rhs_mode"] == 2
 
 
+def _stage_segments_expected(s, stage_of_row):
+    """Stages of L_B that the packer should run whole on one wave: at least
+    two levels of L_B and at most 4 segment tiles (4 terms a lane, 64 lanes)
+    per level on average."""
+    n, rp, ci = s.n, s.row_ptr, s.col_idx
+    lev = np.zeros(n, dtype=np.int64)
+    xt = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        cols = ci[rp[i]:rp[i + 1]]
+        same = cols[(cols != i) & (stage_of_row[cols] == stage_of_row[i])]
+        xt[i] = len(same)
+        lev[i] = 1 + lev[same].max() if len(same) else 0
+    count = 0
+    for st in np.unique(stage_of_row):
+        rows = np.nonzero(stage_of_row == st)[0]
+        tiles, depth = 0, 0
+        for l in np.unique(lev[rows]):
+            r = rows[lev[rows] == l]
+            mx = xt[r].max()
+            lg = next(g for g in range(7) if mx <= 4 << g)
+            tiles += -(-len(r) // (64 >> lg))
+            depth += 1
+        count += depth >= 2 and tiles <= 4 * depth
+    return count
+
+
+@pytest.mark.parametrize("make,depth", [
+    (lambda: wl.banded(4000, 200, 8, 24, seed=9), 16),
+    (lambda: wl.banded(6007, 100, 2, 6, seed=10), 64),
+    (lambda: wl.stencil3d(20, seed=11), 2),
+    (lambda: wl.powerlaw(20011, 500, seed=12), 8),
+])
+def test_stage_segments(sp, make, depth):
+    """In the stage solve, narrow stages run whole on one wave each (their
+    count recomputed here from the stage of every level and the levels of
+    L_B), and only in that solve."""
+    s = make()
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+    plan.rewrite("threshold", max_width=INF, max_depth=depth, max_fill=40.0).set_rhs_mode("stage")
+    sol, _ = plan.stages()
+    want = _stage_segments_expected(s, sol[plan.levels(0)])
+    i = plan.info()
+    print(s.name, i["stages"], want, i["rhs_segments"])
+    assert i["rhs_mode"] == 2 and i["rhs_segments"] == want
+    assert plan.set_rhs_mode("mpass").info()["rhs_segments"] == 0
+
+
 def test_tiling_knob(sp):
     """Terms per lane change the tile shapes only: more terms per lane pack
     more rows per tile (fewer tiles); the rewritten system is unchanged."""
