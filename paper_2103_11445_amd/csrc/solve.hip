@@ -167,11 +167,13 @@ __device__ inline bool pending(const SolveArgs<T> &a, int32_t k, typename Val<T>
 // Waits for every gathered x-term that was not yet published.  The test is a
 // wave-wide vote: with a lane-divergent branch the compiler would drain every
 // load in flight (the prefetches too) before it on all paths.
-//   kElect (wide tiles): while terms are pending, one elected lane polls one
-//     of its pending terms; once that value appears every lane re-reads its
-//     pending terms once.  The rows a wide tile waits on finish at about the
-//     same time, so this costs little latency and keeps the polling traffic
-//     to one lane per waiting wave (waves run ahead of the frontier).
+//   kElect (wide tiles): one elected lane polls one of its pending terms
+//     until it appears, which keeps the polling traffic to one lane per
+//     waiting wave while nothing is ready (waves run ahead of the frontier).
+//     The rows a wide tile waits on finish at about the same time, so that
+//     first arrival opens a burst: from then on every lane re-reads its
+//     pending terms each round until none is left, so the wave sees the last
+//     of them within one round trip of its publication.
 //   otherwise (segments, which rarely wait and then on a single row just
 //     produced by another wave): every pending lane polls its own term.
 template <int kN, bool kElect, typename T>
@@ -180,32 +182,40 @@ __device__ inline void resolve_pending(const SolveArgs<T> &a, const int32_t *col
 #pragma unroll
     for (int c = 0; c < kN; ++c) any |= pending(a, col[c], g[c]);
     unsigned long long mask = __ballot(any);
+    if (!mask) return;
     if (!kElect) {
-        if (mask) {
 #pragma unroll
-            for (int c = 0; c < kN; ++c)
-                if (pending(a, col[c], g[c])) g[c] = wait_slow(a.x, col[c], a.ws, a.wait_limit);
-        }
+        for (int c = 0; c < kN; ++c)
+            if (pending(a, col[c], g[c])) g[c] = wait_slow(a.x, col[c], a.ws, a.wait_limit);
         return;
     }
-    while (mask) {
-        const int leader = __ffsll((long long)mask) - 1;
-        if ((int)(threadIdx.x & 63) == leader) {
-            bool done = false;
+    const int leader = __ffsll((long long)mask) - 1;
+    if ((int)(threadIdx.x & 63) == leader) {
+        bool done = false;
 #pragma unroll
-            for (int c = 0; c < kN; ++c)
-                if (!done && pending(a, col[c], g[c])) {
-                    g[c] = wait_slow(a.x, col[c], a.ws, a.wait_limit);
-                    done = true;
-                }
-        }
+        for (int c = 0; c < kN; ++c)
+            if (!done && pending(a, col[c], g[c])) {
+                g[c] = wait_slow(a.x, col[c], a.ws, a.wait_limit);
+                done = true;
+            }
+    }
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
         any = false;
 #pragma unroll
         for (int c = 0; c < kN; ++c) {
             if (pending(a, col[c], g[c])) g[c] = load_agent(a.x + col[c]);
             any |= pending(a, col[c], g[c]);
         }
-        mask = __ballot(any);
+        if (!__ballot(any)) return;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > a.wait_limit) {
+            // give up like wait_slow: mark the status word, take a quiet NaN
+#pragma unroll
+            for (int c = 0; c < kN; ++c)
+                if (pending(a, col[c], g[c])) g[c] = wait_slow(a.x, col[c], a.ws, 0ull);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
     }
 }
 
