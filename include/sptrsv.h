@@ -311,6 +311,9 @@ typedef struct {
     int32_t rhs_segments;/* stage solve: stages solved whole by one wave each
                             (no wait on another wave); the others run level
                             by level across the grid */
+    int32_t reg_chunks;  /* 64-lane chunks of a wide tile the solve holds in
+                            registers, its terms gathered before the wait
+                            (4, or 8 when most tiles have more than 4) */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

@@ -476,6 +476,7 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->precision = p.precision;
     o->seg_tiles = p.nseg_tiles;
     o->rhs_segments = p.sub ? p.sub->comp_segs : 0;
+    o->reg_chunks = p.layout.reg_chunks;
     return SPTRSV_OK;
 }
 

@@ -357,6 +357,14 @@ void pack(Plan &p) {
     Layout &Ly = p.layout;
     Ly = Layout{};
     Ly.value_bytes = (int)vb;
+    // the kernel instance that holds 8 chunks of a wide tile in registers
+    // when most tiles need more than 4 (their terms are then gathered before
+    // the dependency wait instead of streamed after it)
+    {
+        int64_t longer = 0;
+        for (const Tile &T : tiles) longer += T.nch > 4 ? 1 : -1;
+        Ly.reg_chunks = longer > 0 ? 8 : 4;
+    }
     size_t off = 0;
     Ly.workspace = off;
     off = align256(off + sizeof(Workspace));

@@ -46,6 +46,7 @@ struct Layout;
 // are FP64, or FP32 in a plan stored in FP32 (value_bytes 4).
 struct Layout {
     int value_bytes = 8;
+    int reg_chunks = 4;  // wide-tile chunks the solve kernel holds in registers (4 or 8)
     int32_t rhs_mode = kRhsNone;
     size_t sub = 0;               // kRhsStage: offset of the stage system's image
     const Layout *sub_layout = nullptr;

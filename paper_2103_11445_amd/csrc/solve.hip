@@ -57,7 +57,8 @@
 namespace {
 
 constexpr int32_t kPad = INT32_MIN;
-constexpr int kRegChunks = 4;  // chunks of a wide tile held in registers; more are streamed
+// chunks of a wide tile held in registers (more are streamed): kernel
+// instances for 4 and 8, chosen per plan by the packer (Layout::reg_chunks)
 constexpr int kDepth = sptrsv::kSegDepth;  // segment pipeline depth (tiles)
 constexpr int kSegChunks = sptrsv::kSegChunks;
 constexpr int kRing = sptrsv::kRing;
@@ -337,11 +338,11 @@ __global__ void __launch_bounds__(256) prepare(PrepArgs<T> a) {
 // Registers of one wide tile as seen by one lane.  They hold loads in
 // flight: nothing touches them until the tile is processed, so pads and
 // inactive lanes read a dummy address and are masked at use.
-template <typename T>
+template <typename T, int kReg>
 struct Tile {
     int4 d;                     // {chunk offset, slot offset, chunks, nrows << 8 | log2 lanes per row}
-    int32_t col[kRegChunks];    // term columns of this lane, raw
-    T val[kRegChunks];          // term coefficients, raw
+    int32_t col[kReg];          // term columns of this lane, raw
+    T val[kReg];                // term coefficients, raw
     int32_t row;                // row id of the lane's slot, raw
     T diag;
 };
@@ -350,22 +351,22 @@ __device__ inline bool tile_active(const int4 d, int lane) { return (lane >> (d.
 __device__ inline bool tile_lead(const int4 d, int lane) {
     return tile_active(d, lane) && (lane & ((1 << (d.w & 0xff)) - 1)) == 0;
 }
-template <typename V>
-__device__ inline int32_t tile_col(const Tile<V> &T, int c, int lane) {
+template <typename V, int kReg>
+__device__ inline int32_t tile_col(const Tile<V, kReg> &T, int c, int lane) {
     return tile_active(T.d, lane) && c < T.d.z ? T.col[c] : kPad;
 }
-template <typename V>
-__device__ inline V tile_val(const Tile<V> &T, int c, int lane) {
+template <typename V, int kReg>
+__device__ inline V tile_val(const Tile<V, kReg> &T, int c, int lane) {
     return tile_active(T.d, lane) && c < T.d.z ? T.val[c] : V(0);
 }
 
-template <typename V>
-__device__ inline void load_tile(const SolveArgs<V> &a, const int4 d, int lane, Tile<V> &T) {
+template <typename V, int kReg>
+__device__ inline void load_tile(const SolveArgs<V> &a, const int4 d, int lane, Tile<V, kReg> &T) {
     T.d = d;
     const bool active = tile_active(d, lane);
     const size_t base = (size_t)d.x * 64 + lane;
 #pragma unroll
-    for (int c = 0; c < kRegChunks; ++c) {
+    for (int c = 0; c < kReg; ++c) {
         const bool ok = active && c < d.z;
         T.col[c] = *(ok ? a.tcol + base + (size_t)c * 64 : a.rows);
         T.val[c] = *(ok ? a.tval + base + (size_t)c * 64 : a.diag);
@@ -499,7 +500,7 @@ __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ri
 
 // ----------------------------------------------------------------- kernel --
 
-template <typename T, bool kStamp>
+template <typename T, bool kStamp, int kReg>
 __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     __shared__ T ring[kRing];
     const int lane = threadIdx.x;
@@ -508,7 +509,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     if (i >= a.nitems) return;
     if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     int4 d = unpack_item(load_item(a, i, lane));
-    Tile<T> cur;
+    Tile<T, kReg> cur;
     if (!is_segment(d)) load_tile(a, d, lane, cur);
     int wnext = load_item(a, i + a.waves, lane);  // raw descriptor of the next item
     for (;;) {
@@ -525,10 +526,10 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         }
         const int4 dnext = unpack_item(wnext);
         // 1. every gather of the current tile in flight
-        int32_t col[kRegChunks];
-        typename Val<T>::Bits g[kRegChunks];
+        int32_t col[kReg];
+        typename Val<T>::Bits g[kReg];
 #pragma unroll
-        for (int c = 0; c < kRegChunks; ++c) {
+        for (int c = 0; c < kReg; ++c) {
             col[c] = tile_col(cur, c, lane);
             g[c] = gather_x(a, col[c]);
         }
@@ -537,41 +538,41 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         // 2. the next tile's terms and the descriptor after it
-        Tile<T> nxt;
+        Tile<T, kReg> nxt;
         const bool nwide = in < a.nitems && !is_segment(dnext);
         load_tile(a, nwide ? dnext : d, lane, nxt);
         const int wnn = load_item(a, inn, lane);
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         // 3. wait for the gathers, accumulate
-        resolve_pending<kRegChunks, true>(a, col, g);
+        resolve_pending<kReg, true>(a, col, g);
         T acc = T(0);
 #pragma unroll
-        for (int c = 0; c < kRegChunks; ++c) acc = fma(tile_val(cur, c, lane), term_value<T>(col[c], g[c]), acc);
-        // 4. rows longer than the register chunks: the rest, kRegChunks
+        for (int c = 0; c < kReg; ++c) acc = fma(tile_val(cur, c, lane), term_value<T>(col[c], g[c]), acc);
+        // 4. rows longer than the register chunks: the rest, kReg
         //    chunks at a time, each group's loads and gathers issued together
         //    (the chunk count is uniform over the wave; pads and inactive
         //    lanes read their own pad slot and count as kPad)
-        for (int c0 = kRegChunks; c0 < cur.d.z; c0 += kRegChunks) {
+        for (int c0 = kReg; c0 < cur.d.z; c0 += kReg) {
             const bool act = tile_active(cur.d, lane);
             const size_t base = (size_t)cur.d.x * 64 + lane;
-            int32_t kc[kRegChunks];
-            T vc[kRegChunks];
-            typename Val<T>::Bits gc[kRegChunks];
+            int32_t kc[kReg];
+            T vc[kReg];
+            typename Val<T>::Bits gc[kReg];
 #pragma unroll
-            for (int u = 0; u < kRegChunks; ++u) {
+            for (int u = 0; u < kReg; ++u) {
                 const size_t idx = base + (size_t)(c0 + u < cur.d.z ? c0 + u : c0) * 64;
                 kc[u] = a.tcol[idx];
                 vc[u] = a.tval[idx];
             }
 #pragma unroll
-            for (int u = 0; u < kRegChunks; ++u) {
+            for (int u = 0; u < kReg; ++u) {
                 if (!act || c0 + u >= cur.d.z) kc[u] = kPad;
                 gc[u] = gather_x(a, kc[u]);
             }
-            resolve_pending<kRegChunks, true>(a, kc, gc);
+            resolve_pending<kReg, true>(a, kc, gc);
 #pragma unroll
-            for (int u = 0; u < kRegChunks; ++u) acc = fma(vc[u], term_value<T>(kc[u], gc[u]), acc);
+            for (int u = 0; u < kReg; ++u) acc = fma(vc[u], term_value<T>(kc[u], gc[u]), acc);
         }
         // 5. row sums across the row's lanes, then x_i
         acc = group_sum(acc, cur.d.w & 0xff);
@@ -755,10 +756,11 @@ SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int
 }
 
 template <typename T, bool kStamp = false>
-hipError_t launch_tiles(SolveArgs<T> a, int waves, hipStream_t s) {
+hipError_t launch_tiles(SolveArgs<T> a, int waves, int reg_chunks, hipStream_t s) {
     void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(solve_tiles<T, kStamp>), dim3(waves),
-                                      dim3(64), args, 0, s);
+    const void *k = reg_chunks == 8 ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8>)
+                                    : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4>);
+    return hipLaunchCooperativeKernel(k, dim3(waves), dim3(64), args, 0, s);
 }
 
 template <typename T>
@@ -806,14 +808,14 @@ hipError_t solve_once(const unsigned char *dev, const sptrsv::Layout *lay, int32
             SolveArgs<T> sa = solve_args<T>(dev + lay->sub, lay->sub_layout, n, sub_nitems, sub_waves, wait_limit,
                                             b, y, skip);
             sa.ws = reinterpret_cast<sptrsv::Workspace *>(d + lay->workspace);
-            if ((e = launch_tiles<T, false>(sa, sub_waves, s)) != hipSuccess) return e;
+            if ((e = launch_tiles<T, false>(sa, sub_waves, lay->sub_layout->reg_chunks, s)) != hipSuccess) return e;
             rhs = y;
             bscale = 1;
         }
     }
     SolveArgs<T> a = solve_args<T>(dev, lay, n, nitems, waves, wait_limit, rhs, x, skip, stamps, start_slot);
     a.bscale = bscale;
-    return launch_tiles<T, kStamp>(a, waves, s);
+    return launch_tiles<T, kStamp>(a, waves, lay->reg_chunks, s);
 }
 
 }  // namespace
@@ -824,16 +826,21 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
     if (e != hipSuccess) return (int)e;
     e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return (int)e;
-    // the FP64 instance holds the larger LDS ring, so it bounds residency
-    int b64 = 0, b32 = 0;
-    int bst = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, solve_tiles<double, false>, 64, 0);
-    if (e != hipSuccess) return (int)e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, solve_tiles<float, false>, 64, 0);
-    if (e != hipSuccess) return (int)e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bst, solve_tiles<double, true>, 64, 0);
-    if (e != hipSuccess) return (int)e;
-    *max_waves_per_cu = std::min(std::min(b64, b32), bst);
+    // every instance a plan may launch must be co-resident at this count
+    const void *inst[] = {reinterpret_cast<const void *>(solve_tiles<double, false, 4>),
+                          reinterpret_cast<const void *>(solve_tiles<double, false, 8>),
+                          reinterpret_cast<const void *>(solve_tiles<float, false, 4>),
+                          reinterpret_cast<const void *>(solve_tiles<float, false, 8>),
+                          reinterpret_cast<const void *>(solve_tiles<double, true, 4>),
+                          reinterpret_cast<const void *>(solve_tiles<double, true, 8>)};
+    int most = INT32_MAX;
+    for (const void *k : inst) {
+        int b = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, 64, 0);
+        if (e != hipSuccess) return (int)e;
+        most = std::min(most, b);
+    }
+    *max_waves_per_cu = most;
     return 0;
 }
 

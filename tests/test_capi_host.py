@@ -513,6 +513,19 @@ def test_stage_segments(sp, make, depth):
     assert plan.set_rhs_mode("mpass").info()["rhs_segments"] == 0
 
 
+def test_register_chunks_choice(sp):
+    """The solve holds 8 chunks of a wide tile in registers when most tiles
+    need more than 4 (8 terms per lane give rows 4 < len / lanes <= 8), else
+    4; the choice follows the tiling and never changes the rewrite."""
+    s = wl.banded(4000, 200, 8, 24, seed=9)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", max_width=INF, max_depth=16, max_fill=12.0)
+    assert plan.info()["reg_chunks"] == 4
+    assert plan.set_tiling(8).info()["reg_chunks"] == 8
+    assert plan.set_tiling(2).info()["reg_chunks"] == 4
+    st = wl.stencil3d(16, seed=3)
+    assert sp.Plan(st.row_ptr, st.col_idx, st.val).set_tiling(8).info()["reg_chunks"] == 4
+
+
 def test_tiling_knob(sp):
     """Terms per lane change the tile shapes only: more terms per lane pack
     more rows per tile (fewer tiles); the rewritten system is unchanged."""

@@ -105,6 +105,28 @@ def test_fp32_solve_within_rounding_bound(torch, sp, make, kind, kw):
     assert np.all(np.isfinite(xh)) and ratio <= 1.0
 
 
+@pytest.mark.parametrize("tpl", [8, 16])
+def test_fp32_solve_eight_register_chunks(torch, sp, tpl):
+    """The kernel instance holding 8 chunks of a wide tile in registers (rows
+    of 5..8 chunks, and longer ones streamed 8 chunks at a time), in FP32."""
+    s = wl.fp32_valued(wl.banded(9001, 200, 8, 24, seed=27))
+    b32 = s.b.astype(np.float32)
+    b = b32.astype(np.float64)
+    x = oracle.solve(s.row_ptr, s.col_idx, s.val, b)
+    kw = {"max_width": 10**9, "max_depth": 16, "max_fill": 12.0}
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).set_precision(32).rewrite("threshold", **kw)
+    plan.set_tiling(tpl).upload()
+    assert plan.info()["reg_chunks"] == 8
+    bd = torch.from_numpy(b32).cuda()
+    xd = torch.full_like(bd, float("nan"))
+    plan.solve_fp32(bd, xd)
+    assert plan.check() == 0
+    xh = xd.cpu().numpy().astype(np.float64)
+    ratio = float(np.max(np.abs(xh - x) / np.maximum(fp32_bound(s, b, x, {"kind": "threshold", **kw}), 1e-300)))
+    print(s.name, tpl, "fp32 err/bound", ratio, flush=True)
+    assert np.all(np.isfinite(xh)) and ratio <= 1.0
+
+
 def _refine(torch, sp, plan, b, iterations=10, tol=1e-14):
     bd = torch.from_numpy(np.ascontiguousarray(b).reshape(-1)).cuda()
     xd = torch.full_like(bd, float("nan"))

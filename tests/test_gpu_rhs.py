@@ -130,5 +130,5 @@ def test_tilings_match_oracle(torch, sp, make, tpl):
     x = plan.solve(torch.from_numpy(s.b).cuda())
     assert plan.check() == 0
     err = errors(x.cpu().numpy(), ref)
-    print(s.name, tpl, plan.info()["tiles"], err, flush=True)
+    print(s.name, tpl, plan.info()["tiles"], plan.info()["reg_chunks"], err, flush=True)
     assert err[1] <= TOL
