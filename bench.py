@@ -66,7 +66,7 @@ DEEPER = {"depth256": "depth512"}
 # Result of the tuning leg on MI355X (used by --no-tune, e.g. under a profiler).
 TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth512", "powerlaw_4m": "paper256",
          "stencil2d_100": "paper"}
-TUNED_TILING = {"stencil3d_128": 4, "banded_1m": 8, "powerlaw_4m": 2, "stencil2d_100": 4}
+TUNED_TILING = {"stencil3d_128": 8, "banded_1m": 8, "powerlaw_4m": 2, "stencil2d_100": 4}
 TUNED_WAVES = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
 
 
@@ -251,7 +251,7 @@ def main():
         # row-to-wavefront tiling of the chosen plan
         tiling[n] = 4
         best_ms = best[0]
-        for tpl in (2, 8):
+        for tpl in (2, 8, 16):
             p = plans[n].set_tiling(tpl)
             p._buf = None
             p.upload()
