@@ -201,7 +201,7 @@ __device__ inline void resolve_pending(const SolveArgs<T> &a, const int32_t *col
             }
     }
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-    for (;;) {
+    for (unsigned it = 1;; ++it) {
         any = false;
 #pragma unroll
         for (int c = 0; c < kN; ++c) {
@@ -209,11 +209,14 @@ __device__ inline void resolve_pending(const SolveArgs<T> &a, const int32_t *col
             any |= pending(a, col[c], g[c]);
         }
         if (!__ballot(any)) return;
-        if (__builtin_amdgcn_s_memrealtime() - t0 > a.wait_limit) {
-            // give up like wait_slow: mark the status word, take a quiet NaN
+        // give up like wait_slow: past the wait limit (marking the status
+        // word), or once another wait has given up, take a quiet NaN
+        const bool late = __builtin_amdgcn_s_memrealtime() - t0 > a.wait_limit;
+        if (late || ((it & 15u) == 0 && __hip_atomic_load(&a.ws->status, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
 #pragma unroll
             for (int c = 0; c < kN; ++c)
-                if (pending(a, col[c], g[c])) g[c] = wait_slow(a.x, col[c], a.ws, 0ull);
+                if (pending(a, col[c], g[c])) g[c] = late ? wait_slow(a.x, col[c], a.ws, 0ull) : Val<T>::kQuietNaN;
             return;
         }
         __builtin_amdgcn_s_sleep(1);
