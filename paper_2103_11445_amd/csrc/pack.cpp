@@ -24,6 +24,9 @@
 // segment, executed by one wave from first tile to last: dependencies on
 // rows of the same segment produced at most kRing rows earlier are read
 // from the wave's LDS ring (column n + ring index) instead of global memory.
+// A segment whose terms all come from the ring is flagged in its descriptor
+// and gathers nothing but the constants; its pads point at the ring's zero
+// slot (column n + kRing).
 // Segment tiles are stored with a fixed stride, lane-major (each lane's
 // kSegChunks columns, then its coefficients, contiguous; one row id / meta
 // pair and one diagonal per lane) so the wave prefetches a tile with a few
@@ -470,13 +473,14 @@ void pack(Plan &p) {
     };
 
     int32_t sid = -1;
+    bool all_ring = true;
     for (size_t it = 0; it < items.size(); ++it) {
         const Item &I = items[it];
         if (I.kind == 1) {
             ++sid;
+            bool ring_only = true;  // every term read from the LDS ring
             desc[4 * it + 0] = (int32_t)I.a;
             desc[4 * it + 1] = (int32_t)I.b;
-            desc[4 * it + 2] = 0;
             desc[4 * it + 3] = (int32_t)0x80000000u;
             for (int64_t st = I.a; st < I.a + I.b; ++st) {
                 const SegTile &T = stiles[(size_t)st];
@@ -495,10 +499,17 @@ void pack(Plan &p) {
                         const int64_t idx = ln * kSegChunks + (t_ >> T.lg);
                         scol[idx] = col;
                         putv(Ly.sval, idx, v);
+                        ring_only = ring_only && col >= n;
                         ++t_;
                     });
                 }
             }
+            // a segment without gathers: its pads read the ring's zero slot
+            desc[4 * it + 2] = ring_only ? 1 : 0;
+            all_ring = all_ring && ring_only;
+            if (ring_only)
+                for (int64_t q = I.a * 64 * kSegChunks; q < (I.a + I.b) * 64 * kSegChunks; ++q)
+                    if (scol[q] == kPad) scol[q] = n + kRing;
             continue;
         }
         const Tile &T = tiles[(size_t)I.a];
@@ -518,6 +529,7 @@ void pack(Plan &p) {
             });
         }
     }
+    Ly.ring_segs = nseg > 0 && all_ring ? 1 : 0;
     if (rhs_mode == kRhsMPass) {
         // M tiles: b-terms (device index of b_j, coefficient M_ij)
         int32_t *mdesc = reinterpret_cast<int32_t *>(img + Ly.mtiles);

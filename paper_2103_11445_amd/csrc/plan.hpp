@@ -47,6 +47,7 @@ struct Layout;
 struct Layout {
     int value_bytes = 8;
     int reg_chunks = 4;  // wide-tile chunks the solve kernel holds in registers (4 or 8)
+    int ring_segs = 0;   // every segment reads only its LDS ring (the lighter kernel instance)
     int32_t rhs_mode = kRhsNone;
     size_t sub = 0;               // kRhsStage: offset of the stage system's image
     const Layout *sub_layout = nullptr;
@@ -58,6 +59,7 @@ struct Layout {
     size_t tcol = 0;       // int32[64*nchunks] term column (0..n-1 x-term, ~j b-term, INT32_MIN pad)
     size_t tval = 0;       // double[64*nchunks] term coefficient (x-terms negated)
     size_t scol = 0;       // int32[nseg_tiles][64][kSegChunks] as tcol, plus n + ring index for LDS x-terms
+                           // (n + kRing, a zero slot, for the pads of a segment without gathers)
     size_t sval = 0;       // double[nseg_tiles][64][kSegChunks]
     size_t srow = 0;       // int32[nseg_tiles][64][2]: row finished by the lane (-1 if none),
                            //   log2 lanes per row | ring index << 8

@@ -229,16 +229,18 @@ __device__ inline T term_value(int32_t k, typename Val<T>::Bits v) {
     return k == kPad ? T(0) : Val<T>::of(v);
 }
 
+// (the permutes used here read a lane of the same row for every lane, so no
+// lane keeps an old value and none needs to be supplied)
 template <int kCtrl>
 __device__ inline double dpp_add(double v) {
     const long long bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffff), kCtrl, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), kCtrl, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffff), kCtrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), kCtrl, 0xf, 0xf, false);
     return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <int kCtrl>
 __device__ inline float dpp_add(float v) {
-    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), kCtrl, 0xf, 0xf, false));
 }
 
 // Sum over aligned groups of 2^lg lanes (every lane of a group gets the sum).
@@ -426,14 +428,18 @@ __device__ inline void seg_load(const SolveArgs<T> &a, long long st, int lane, S
     S.diag = a.sdiag[ln];
 }
 
-template <typename T>
+// kRingOnly: a segment whose terms are all LDS-ring terms (and pads, which
+// read the ring's zero slot), so nothing is gathered but the constant.
+template <typename T, bool kRingOnly>
 __device__ inline void seg_gather(const SolveArgs<T> &a, SegSlot<T> &S) {
+    if (!kRingOnly) {
 #pragma unroll
-    for (int c = 0; c < kSegChunks; ++c) S.g[c] = gather_x(a, seg_col(S, c));
+        for (int c = 0; c < kSegChunks; ++c) S.g[c] = gather_x(a, seg_col(S, c));
+    }
     S.bi = Val<T>::of(load_at(a.b, S.rm.x >= 0 ? S.rm.x : 0));
 }
 
-template <typename T>
+template <typename T, bool kRingOnly>
 __device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring) {
     int32_t col[kSegChunks];
 #pragma unroll
@@ -442,15 +448,24 @@ __device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring)
     // slot and discard it): the reads go out together, with one wait,
     // instead of one branch and one wait per chunk
     T rv[kSegChunks];
-#pragma unroll
-    for (int c = 0; c < kSegChunks; ++c) rv[c] = ring[((uint32_t)col[c] - (uint32_t)a.n) & (kRing - 1)];
-    resolve_pending<kSegChunks, false>(a, col, S.g);
     T acc = T(0);
+    if (kRingOnly) {
+        // columns n + slot, pads n + kRing (the zero slot)
 #pragma unroll
-    for (int c = 0; c < kSegChunks; ++c) {
-        const int32_t k = col[c];
-        const T v = k >= a.n ? rv[c] : term_value<T>(k, S.g[c]);
-        acc = fma(seg_val(S, c), v, acc);
+        for (int c = 0; c < kSegChunks; ++c) rv[c] = ring[(uint32_t)col[c] - (uint32_t)a.n];
+#pragma unroll
+        for (int c = 0; c < kSegChunks; ++c) acc = fma(seg_val(S, c), rv[c], acc);
+    } else {
+#pragma unroll
+        for (int c = 0; c < kSegChunks; ++c)
+            rv[c] = ring[min((uint32_t)col[c] - (uint32_t)a.n, (uint32_t)kRing)];
+        resolve_pending<kSegChunks, false>(a, col, S.g);
+#pragma unroll
+        for (int c = 0; c < kSegChunks; ++c) {
+            const int32_t k = col[c];
+            const T v = k >= a.n ? rv[c] : term_value<T>(k, S.g[c]);
+            acc = fma(seg_val(S, c), v, acc);
+        }
     }
     acc = group_sum(acc, __builtin_amdgcn_readfirstlane(S.rm.y) & 0xff);
     if (S.rm.x >= 0) {
@@ -471,7 +486,7 @@ __device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring)
 // loads are harmless and keep the load count per step fixed).  The compiler
 // barriers keep every stage where it is written: left to itself the
 // scheduler sinks the prefetch loads down to their use.
-template <typename T, bool kStamp>
+template <typename T, bool kStamp, bool kRingOnly>
 __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ring) {
     const long long first = d.x, count = d.y, last = first + count - 1;
     SegSlot<T> S[kDepth];
@@ -480,18 +495,18 @@ __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ri
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int k = 0; k < kDepth / 2; ++k) seg_gather(a, S[k]);
+    for (int k = 0; k < kDepth / 2; ++k) seg_gather<T, kRingOnly>(a, S[k]);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     for (long long base = 0; base < count; base += kDepth) {
 #pragma unroll
         for (int k = 0; k < kDepth; ++k) {
             const long long t = base + k;
-            seg_finish(a, S[k], ring);
+            seg_finish<T, kRingOnly>(a, S[k], ring);
             if (kStamp && lane == 0) a.stamps[a.nitems + first + t] = __builtin_amdgcn_s_memrealtime();
             asm volatile("" ::: "memory");
             __builtin_amdgcn_sched_barrier(0);
-            seg_gather(a, S[(k + kDepth / 2) % kDepth]);
+            seg_gather<T, kRingOnly>(a, S[(k + kDepth / 2) % kDepth]);
             asm volatile("" ::: "memory");
             __builtin_amdgcn_sched_barrier(0);
             seg_load(a, min(first + t + kDepth, last), lane, S[k]);
@@ -503,11 +518,15 @@ __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ri
 
 // ----------------------------------------------------------------- kernel --
 
-template <typename T, bool kStamp, int kReg>
+// kRingSegs: every segment of the plan is flagged ring-only, and the
+// instance carries only that (lighter) segment loop; otherwise the general
+// loop runs every segment, ring-only ones included.
+template <typename T, bool kStamp, int kReg, bool kRingSegs>
 __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
-    __shared__ T ring[kRing];
+    __shared__ T ring[kRing + 1];  // x of the segment's last kRing rows, then a zero slot
     const int lane = threadIdx.x;
     long long i = blockIdx.x;
+    if (lane == 0) ring[kRing] = T(0);
     if (kStamp && i == 0 && lane == 0) a.stamps[a.start_slot] = __builtin_amdgcn_s_memrealtime();
     if (i >= a.nitems) return;
     if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
@@ -518,7 +537,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     for (;;) {
         const long long in = i + a.waves, inn = in + a.waves;
         if (is_segment(d)) {
-            run_segment<T, kStamp>(a, d, lane, ring);
+            run_segment<T, kStamp, kRingSegs>(a, d, lane, ring);
             if (kStamp && lane == 0) a.stamps[i] = __builtin_amdgcn_s_memrealtime();
             if (in >= a.nitems) break;
             d = unpack_item(wnext);
@@ -758,12 +777,21 @@ SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int
     return a;
 }
 
+template <typename T, bool kStamp>
+const void *tiles_kernel(const sptrsv::Layout *lay) {
+    // the instrumented solve runs every plan with the general segment loop
+    const bool ring = !kStamp && lay->ring_segs;
+    if (lay->reg_chunks == 8)
+        return ring ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8, !kStamp>)
+                    : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8, false>);
+    return ring ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4, !kStamp>)
+                : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4, false>);
+}
+
 template <typename T, bool kStamp = false>
-hipError_t launch_tiles(SolveArgs<T> a, int waves, int reg_chunks, hipStream_t s) {
+hipError_t launch_tiles(SolveArgs<T> a, int waves, const sptrsv::Layout *lay, hipStream_t s) {
     void *args[] = {&a};
-    const void *k = reg_chunks == 8 ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8>)
-                                    : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4>);
-    return hipLaunchCooperativeKernel(k, dim3(waves), dim3(64), args, 0, s);
+    return hipLaunchCooperativeKernel(tiles_kernel<T, kStamp>(lay), dim3(waves), dim3(64), args, 0, s);
 }
 
 template <typename T>
@@ -811,14 +839,14 @@ hipError_t solve_once(const unsigned char *dev, const sptrsv::Layout *lay, int32
             SolveArgs<T> sa = solve_args<T>(dev + lay->sub, lay->sub_layout, n, sub_nitems, sub_waves, wait_limit,
                                             b, y, skip);
             sa.ws = reinterpret_cast<sptrsv::Workspace *>(d + lay->workspace);
-            if ((e = launch_tiles<T, false>(sa, sub_waves, lay->sub_layout->reg_chunks, s)) != hipSuccess) return e;
+            if ((e = launch_tiles<T, false>(sa, sub_waves, lay->sub_layout, s)) != hipSuccess) return e;
             rhs = y;
             bscale = 1;
         }
     }
     SolveArgs<T> a = solve_args<T>(dev, lay, n, nitems, waves, wait_limit, rhs, x, skip, stamps, start_slot);
     a.bscale = bscale;
-    return launch_tiles<T, kStamp>(a, waves, lay->reg_chunks, s);
+    return launch_tiles<T, kStamp>(a, waves, lay, s);
 }
 
 }  // namespace
@@ -830,12 +858,16 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
     e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return (int)e;
     // every instance a plan may launch must be co-resident at this count
-    const void *inst[] = {reinterpret_cast<const void *>(solve_tiles<double, false, 4>),
-                          reinterpret_cast<const void *>(solve_tiles<double, false, 8>),
-                          reinterpret_cast<const void *>(solve_tiles<float, false, 4>),
-                          reinterpret_cast<const void *>(solve_tiles<float, false, 8>),
-                          reinterpret_cast<const void *>(solve_tiles<double, true, 4>),
-                          reinterpret_cast<const void *>(solve_tiles<double, true, 8>)};
+    const void *inst[] = {reinterpret_cast<const void *>(solve_tiles<double, false, 4, false>),
+                          reinterpret_cast<const void *>(solve_tiles<double, false, 8, false>),
+                          reinterpret_cast<const void *>(solve_tiles<double, false, 4, true>),
+                          reinterpret_cast<const void *>(solve_tiles<double, false, 8, true>),
+                          reinterpret_cast<const void *>(solve_tiles<float, false, 4, false>),
+                          reinterpret_cast<const void *>(solve_tiles<float, false, 8, false>),
+                          reinterpret_cast<const void *>(solve_tiles<float, false, 4, true>),
+                          reinterpret_cast<const void *>(solve_tiles<float, false, 8, true>),
+                          reinterpret_cast<const void *>(solve_tiles<double, true, 4, false>),
+                          reinterpret_cast<const void *>(solve_tiles<double, true, 8, false>)};
     int most = INT32_MAX;
     for (const void *k : inst) {
         int b = 0;
