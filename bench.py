@@ -248,10 +248,10 @@ def main():
                 queue.append(DEEPER[best[2]])
         _, plans[n], chosen[n], h = best
         host[n].update(h)
-        # row-to-wavefront tiling of the chosen plan
-        tiling[n] = 4
-        best_ms = best[0]
-        for tpl in (2, 8, 16):
+        # row-to-wavefront tiling of the chosen plan: the recorded tuning (for
+        # the recorded policy, else 4 terms per lane) is kept unless another
+        # tiling is faster by more than 3%
+        def retile(tpl):
             p = plans[n].set_tiling(tpl)
             p._buf = None
             p.upload()
@@ -259,7 +259,14 @@ def main():
             tuning[n][f"{chosen[n]}/t{tpl}"] = {"ms": ms, "levels_rw": p.info()["levels_rw"],
                                                "entries": tuning[n][chosen[n]]["entries"], "status": p.check()}
             log(f"[tune] {n} {chosen[n]} terms/lane {tpl}: {ms:.3f} ms")
-            if ms < best_ms:
+            return ms
+        tiling[n] = TUNED_TILING.get(n, 4) if chosen[n] == TUNED.get(n) else 4
+        best_ms = best[0] if tiling[n] == 4 else retile(tiling[n])
+        for tpl in (2, 4, 8, 16):
+            if tpl == tiling[n]:
+                continue
+            ms = retile(tpl)
+            if ms < 0.97 * best_ms:
                 best_ms, tiling[n] = ms, tpl
         plans[n].set_tiling(tiling[n])
         plans[n]._buf = None
