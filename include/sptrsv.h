@@ -314,6 +314,11 @@ typedef struct {
     int32_t reg_chunks;  /* 64-lane chunks of a wide tile the solve holds in
                             registers, its terms gathered before the wait
                             (4, or 8 when most tiles have more than 4) */
+    int32_t segments;    /* segments of the schedule (seg_tiles is their
+                            tiles) */
+    int32_t ring_segments;/* of which every term comes from the wave's LDS
+                            ring; when all do, the solve runs a lighter
+                            segment loop that gathers only the constants */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

@@ -57,7 +57,8 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("seg_tiles", ctypes.c_int64),
                 ("rhs_mode", ctypes.c_int32), ("nnz_rhs", ctypes.c_int64),
-                ("rhs_segments", ctypes.c_int32), ("reg_chunks", ctypes.c_int32)]
+                ("rhs_segments", ctypes.c_int32), ("reg_chunks", ctypes.c_int32),
+                ("segments", ctypes.c_int32), ("ring_segments", ctypes.c_int32)]
 
 
 _lib = None

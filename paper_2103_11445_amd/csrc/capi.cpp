@@ -477,6 +477,8 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->seg_tiles = p.nseg_tiles;
     o->rhs_segments = p.sub ? p.sub->comp_segs : 0;
     o->reg_chunks = p.layout.reg_chunks;
+    o->segments = p.nseg;
+    o->ring_segments = p.ring_segs;
     return SPTRSV_OK;
 }
 

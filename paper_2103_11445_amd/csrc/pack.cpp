@@ -474,6 +474,7 @@ void pack(Plan &p) {
 
     int32_t sid = -1;
     bool all_ring = true;
+    int32_t ring_count = 0;
     for (size_t it = 0; it < items.size(); ++it) {
         const Item &I = items[it];
         if (I.kind == 1) {
@@ -507,6 +508,7 @@ void pack(Plan &p) {
             // a segment without gathers: its pads read the ring's zero slot
             desc[4 * it + 2] = ring_only ? 1 : 0;
             all_ring = all_ring && ring_only;
+            ring_count += ring_only;
             if (ring_only)
                 for (int64_t q = I.a * 64 * kSegChunks; q < (I.a + I.b) * 64 * kSegChunks; ++q)
                     if (scol[q] == kPad) scol[q] = n + kRing;
@@ -595,6 +597,7 @@ void pack(Plan &p) {
     p.nseg = nseg;
     p.nseg_tiles = nst;
     p.comp_segs = comp_segs;
+    p.ring_segs = ring_count;
     p.uploaded = false;
 }
 

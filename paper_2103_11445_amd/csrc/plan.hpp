@@ -152,6 +152,7 @@ struct Plan {
     int32_t nseg = 0;        // segments
     int64_t nseg_tiles = 0;  // tiles inside segments
     int32_t comp_segs = 0;   // segments that are whole independent stages
+    int32_t ring_segs = 0;   // segments whose terms all come from the LDS ring
     // executed level (of L') whose rows each item and each segment tile
     // finish, -1 for segment items and padding tiles: the map of the
     // completion stamps of an instrumented solve

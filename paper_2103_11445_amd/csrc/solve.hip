@@ -17,13 +17,20 @@
 //   * Latency hiding in wide tiles: a wave issues every gather of its current
 //     tile at once (x-terms and the row's constant), then the loads of its
 //     next tile's terms, and only then waits for the gathers; the next
-//     descriptor is fetched two items ahead.
-//   * Segments (runs of narrow levels, e.g. a long serial chain) are one
-//     work item executed by one wave tile after tile.  Rows the segment
-//     produced recently are read from the wave's LDS ring instead of global
-//     memory, and the wave runs a software pipeline: term loads kDepth tiles
-//     ahead, constant / external-x gathers kDepth/2 tiles ahead, so the
-//     critical path waits only on LDS and on loads issued several tiles before.
+//     descriptor is fetched two items ahead.  The wait: one elected lane
+//     polls until a term appears, then the whole wave re-reads its pending
+//     terms each round (the rows a tile waits on finish together).
+//   * Segments (runs of narrow levels, e.g. a long serial chain, or a whole
+//     stage of the stage system) are one work item executed by one wave tile
+//     after tile.  Rows the segment produced recently are read from the
+//     wave's LDS ring instead of global memory, and the wave runs a software
+//     pipeline: term loads kDepth tiles ahead, constant / external-x gathers
+//     kDepth/2 tiles ahead, so the critical path waits only on LDS and on
+//     loads issued several tiles before.  A plan whose segments read only the
+//     ring runs an instance without the external-x machinery.
+//   * Wide tiles keep 4 or 8 chunks of terms in registers (one instance
+//     each, chosen per plan); x and b are addressed by 32-bit offsets from
+//     their base.
 //   * The rewritten right-hand side b' = b + M b depends on nothing the
 //     solve computes, so the solve's tiles hold x-terms only and b' comes
 //     from a step before it: either a fully parallel pass over M (prepare),
@@ -444,8 +451,8 @@ __device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring)
     int32_t col[kSegChunks];
 #pragma unroll
     for (int c = 0; c < kSegChunks; ++c) col[c] = seg_col(S, c);
-    // every chunk reads the ring (terms that are not ring terms read some
-    // slot and discard it): the reads go out together, with one wait,
+    // every chunk reads the ring (terms that are not ring terms read the
+    // zero slot and discard it): the reads go out together, with one wait,
     // instead of one branch and one wait per chunk
     T rv[kSegChunks];
     T acc = T(0);

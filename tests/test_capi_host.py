@@ -526,6 +526,24 @@ def test_register_chunks_choice(sp):
     assert sp.Plan(st.row_ptr, st.col_idx, st.val).set_tiling(8).info()["reg_chunks"] == 4
 
 
+def test_ring_only_segments(sp):
+    """A segment whose every term comes from the LDS ring is counted (and
+    run by the lighter loop when all segments are such): a chain keeps each
+    dependency in the ring, the power-law tail reaches back past its segment."""
+    ch = wl.bidiagonal(5000, seed=43)
+    i = sp.Plan(ch.row_ptr, ch.col_idx, ch.val).info()
+    assert i["segments"] == i["ring_segments"] == 1 and i["seg_tiles"] == 5000
+    pl = wl.powerlaw(50000, 3000, seed=42)
+    i = sp.Plan(pl.row_ptr, pl.col_idx, pl.val).info()
+    assert i["segments"] >= 1 and i["ring_segments"] == 0
+    rl = wl.random_lower(700, 0.6, seed=54)
+    i = sp.Plan(rl.row_ptr, rl.col_idx, rl.val).info()
+    assert 0 < i["ring_segments"] < i["segments"]
+    st = wl.stencil3d(20, seed=41)
+    i = sp.Plan(st.row_ptr, st.col_idx, st.val).info()
+    assert i["segments"] == i["ring_segments"] == 0
+
+
 def test_tiling_knob(sp):
     """Terms per lane change the tile shapes only: more terms per lane pack
     more rows per tile (fewer tiles); the rewritten system is unchanged."""
