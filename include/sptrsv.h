@@ -301,7 +301,8 @@ typedef struct {
     int64_t bytes;       /* of the plain solve */
     int64_t bytes_rw;    /* of the rewritten solve */
     int64_t device_bytes;/* size of the device image + workspace */
-    int64_t tiles;       /* 64-lane work tiles in the device schedule */
+    int64_t tiles;       /* work items of the device schedule: 64-lane wide
+                            tiles, and segments (counted once each) */
     int32_t precision;   /* 64 or 32: value type of the device image */
     int64_t seg_tiles;   /* tiles inside segments (runs of narrow levels one
                             wave executes in order) */
