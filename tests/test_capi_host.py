@@ -526,6 +526,29 @@ def test_register_chunks_choice(sp):
     assert sp.Plan(st.row_ptr, st.col_idx, st.val).set_tiling(8).info()["reg_chunks"] == 4
 
 
+def test_stage_segments_random(sp):
+    """The same count on seeded random matrices of every family and a range
+    of stage depths and fill budgets (stage mode forced)."""
+    rng = np.random.default_rng(2024)
+    makers = [lambda q: wl.banded(int(q.integers(500, 3000)), int(q.integers(20, 200)), 2, 12,
+                                  seed=int(q.integers(1 << 30))),
+              lambda q: wl.powerlaw(int(q.integers(2000, 8000)), int(q.integers(50, 400)),
+                                    seed=int(q.integers(1 << 30))),
+              lambda q: wl.stencil2d(int(q.integers(10, 40)), seed=int(q.integers(1 << 30))),
+              lambda q: wl.random_lower(int(q.integers(50, 300)), float(q.uniform(0.05, 0.5)),
+                                        seed=int(q.integers(1 << 30)))]
+    for trial in range(12):
+        s = makers[trial % len(makers)](rng)
+        depth = int(rng.choice([2, 3, 8, 32, 128]))
+        plan = sp.Plan(s.row_ptr, s.col_idx, s.val)
+        plan.rewrite("threshold", max_width=INF, max_depth=depth, max_fill=float(rng.choice([2.0, 12.0, 60.0])))
+        if plan.info()["nnz_m"] == 0:
+            continue
+        plan.set_rhs_mode("stage")
+        sol, _ = plan.stages()
+        assert plan.info()["rhs_segments"] == _stage_segments_expected(s, sol[plan.levels(0)]), (s.name, depth)
+
+
 def test_ring_only_segments(sp):
     """A segment whose every term comes from the LDS ring is counted (and
     run by the lighter loop when all segments are such): a chain keeps each
