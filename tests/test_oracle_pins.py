@@ -323,6 +323,32 @@ def test_invariants_random(n, density, seed, width, depth, fill):
     assert np.all(np.abs(xr - x) <= 1e-12 * np.maximum(np.abs(x), floor))
 
 
+@settings(max_examples=40, deadline=None, derandomize=True)
+@given(n=st.integers(2, 150), density=st.floats(0.01, 0.4), seed=st.integers(0, 10**6),
+       depth=st.integers(2, 30), fill=st.floats(0.5, 8.0))
+def test_stage_rhs_identity(n, density, seed, depth, fill):
+    """The right-hand side of the rewritten rows, b' = b + M b, equals D y
+    with L_B y = b, L_B the entries of L whose two levels share a stage and D
+    the diagonal (Sec. III: within a stage the rewriting eliminates exactly
+    the in-stage couplings, so (I + M) restricted to a stage is D L_SS^-1).
+    Both sides from the oracle: its M, and its solve of the block system."""
+    s = wl.random_lower(n, density, seed=seed)
+    pol = {"kind": "threshold", "max_width": 10**9, "max_depth": depth, "max_fill": fill}
+    p = oracle.plan(s.row_ptr, s.col_idx, s.val, pol)
+    stage = p["stage_of_level"][p["level"]]
+    rows = np.repeat(np.arange(n), np.diff(s.row_ptr))
+    keep = stage[rows] == stage[s.col_idx]
+    bp = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(np.bincount(rows[keep], minlength=n), out=bp[1:])
+    y = oracle.solve(bp, s.col_idx[keep].astype(np.int32), s.val[keep], s.b)
+    m_ptr, m_col, m_val = p["m"]
+    mb = np.array([np.dot(m_val[m_ptr[i]:m_ptr[i + 1]], s.b[m_col[m_ptr[i]:m_ptr[i + 1]]]) for i in range(n)])
+    diag = s.val[s.row_ptr[1:] - 1]
+    lhs, rhs = s.b + mb, diag * y
+    floor = 1e-3 * np.max(np.abs(rhs))
+    assert np.all(np.abs(lhs - rhs) <= 1e-12 * np.maximum(np.abs(rhs), floor))
+
+
 def test_long_double_is_closer_to_exact():
     """The extended-precision twin is at least as close to the exact
     solution as the FP64 oracle (sampled rows of a 2D stencil)."""
