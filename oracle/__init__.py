@@ -19,7 +19,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB points the loader at another build of oracle.c; the mutation
+# check (tests/oracle_mutations.py) uses it to run the pins against copies of
+# the oracle with a planted mistake
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 KIND = {"none": 0, "threshold": 1, "explicit": 2}
 
