@@ -28,6 +28,14 @@ MUTANTS = [
     ("stage depth test", r"candidate = width <= max_width && depth < max_depth;",
      "candidate = width <= max_width && depth <= max_depth;"),
     ("b index of a b-term", r"bi = bi \+ m_val\[p\] \* b\[m_col\[p\]\];", "bi = bi + m_val[p] * b[i];"),
+    ("sign in the long-double solve", r"s = s \+ \(long double\)val\[p\] \* xl\[j\];",
+     "s = s - (long double)val[p] * xl[j];"),
+    ("diagonal test of the backward solve", r"if \(j > i\)\n", "if (j >= i)\n"),
+    ("level-set counts shifted", r"level_ptr\[level\[i\] \+ 1\] \+= 1;", "level_ptr[level[i]] += 1;"),
+    ("width rule < for <=", r"candidate = width <= max_width", "candidate = width < max_width"),
+    ("fill budget < for <=", r"take = added \+ delta <= budget", "take = added + delta < budget"),
+    ("b-terms left out of a level's entries", r"delta \+= nx \+ nb - ", "delta += nx - "),
+    ("sign in the rewritten solve", r"s = s \+ lp_val\[p\] \* x\[k\];", "s = s - lp_val[p] * x[k];"),
 ]
 
 
