@@ -3,8 +3,10 @@
 Plants one plausible mistake at a time in a copy of ``oracle/oracle.c`` (a
 dropped or flipped sign, a wrong index, an off-by-one test), builds the copy
 in a temporary directory and runs ``tests/test_oracle_pins.py`` against it
-through ``ORACLE_LIB``.  Every mutant must make at least one pin fail; the
-repository's own oracle is never touched.
+through ``ORACLE_LIB``; likewise for the cost model's ``oracle/mlp.py`` (a
+copy of the package first on the path) against ``tests/test_oracle_mlp.py``.
+Every mutant must make at least one pin fail; the repository's own oracle is
+never touched.
 
     python tests/oracle_mutations.py
 """
@@ -39,10 +41,52 @@ MUTANTS = [
 ]
 
 
+# mistakes in the cost model's oracle (oracle/mlp.py), checked by
+# tests/test_oracle_mlp.py against a copy of the package placed first on the path
+MLP_MUTANTS = [
+    ("tanh derivative sign", r"\(1\.0 - h2 \*\* 2\)", "(1.0 + h2 ** 2)"),
+    ("factor 2 of the squared error", r"g = 2\.0 \* \(y - t\) / m", "g = (y - t) / m"),
+    ("bias gradient averaged", r'"b1": d1\.sum\(axis=0\)', '"b1": d1.mean(axis=0)'),
+    ("first-layer gradient transposed", r'"W1": d1\.T @ X', '"W1": (X.T @ d1).T.reshape(X.shape[1], -1).T'),
+    ("Adam without bias correction", r"mh = m1 / \(1\.0 - beta1 \*\* step\)", "mh = m1"),
+    ("output bias dropped", r"return h2 @ q\[\"w3\"\] \+ q\[\"b3\"\]\[0\]", "return h2 @ q[\"w3\"]"),
+]
+
+
+def run_pins(test_file, env, cwd=ROOT):
+    # (python -m puts the working directory first on the path: a mutated
+    # package copy is found first only when the run starts in its directory)
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", test_file), "-x", "-q",
+                        "-p", "no:cacheprovider"], env={**os.environ, **env}, cwd=cwd, capture_output=True, text=True)
+    failed = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
+    return r.returncode, (failed[0] if failed else (r.stdout.strip().splitlines() or [""])[-1])
+
+
 def main() -> int:
     src = open(SRC).read()
     survived = 0
     with tempfile.TemporaryDirectory() as tmp:
+        mlp_src = open(os.path.join(ROOT, "oracle", "mlp.py")).read()
+        pkg = os.path.join(tmp, "oracle")
+        os.makedirs(pkg)
+        with open(os.path.join(pkg, "__init__.py"), "w") as f:
+            f.write(open(os.path.join(ROOT, "oracle", "__init__.py")).read())
+        lib_real = os.path.join(ROOT, "oracle", "liboracle.so")
+        for what, pat, rep in MLP_MUTANTS:
+            mutated, count = re.subn(pat, rep, mlp_src, count=1)
+            if count != 1:
+                print(f"NOT APPLIED ({what}): pattern not found")
+                survived += 1
+                continue
+            with open(os.path.join(pkg, "mlp.py"), "w") as f:
+                f.write(mutated)
+            rc, msg = run_pins("test_oracle_mlp.py", {"PYTHONPATH": tmp + os.pathsep + ROOT, "ORACLE_LIB": lib_real},
+                               cwd=tmp)
+            if rc == 0:
+                print(f"SURVIVED ({what})")
+                survived += 1
+            else:
+                print(f"killed ({what}): {msg}")
         for what, pat, rep in MUTANTS:
             mutated, count = re.subn(pat, rep, src, count=1)
             if count != 1:
@@ -55,15 +99,12 @@ def main() -> int:
                 f.write(mutated)
             subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", c, "-o", lib,
                             "-lm"], check=True)
-            r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                                "-x", "-q", "-p", "no:cacheprovider"],
-                               env={**os.environ, "ORACLE_LIB": lib}, cwd=ROOT, capture_output=True, text=True)
-            failed = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
-            if r.returncode == 0:
+            rc, msg = run_pins("test_oracle_pins.py", {"ORACLE_LIB": lib})
+            if rc == 0:
                 print(f"SURVIVED ({what})")
                 survived += 1
             else:
-                print(f"killed ({what}): {failed[0] if failed else r.stdout.strip().splitlines()[-1]}")
+                print(f"killed ({what}): {msg}")
     return 1 if survived else 0
 
 
