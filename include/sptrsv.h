@@ -48,7 +48,8 @@ typedef enum {
     SPTRSV_ERR_DIAG = 3,     /* a row whose last entry is not its diagonal, or a
                                 zero diagonal */
     SPTRSV_ERR_OVERFLOW = 4, /* the rewritten system does not fit int32 device
-                                indexing */
+                                indexing, or n x value bytes reaches 2^32 (x
+                                and b are addressed by 32-bit offsets) */
     SPTRSV_ERR_OOM = 5,      /* host allocation failed */
     SPTRSV_ERR_HIP = 6,      /* a HIP runtime call failed (message has details) */
     SPTRSV_ERR_STATE = 7,    /* solve before upload, or after a rewrite made the
