@@ -57,22 +57,26 @@ void oracle_solve(int n, const int *row_ptr, const int *col_idx,
     }
 }
 
-/* The same substitution carried in long double (x87 extended precision);
- * x_ld holds the extended values, x the values rounded to double. */
+/* The type the extended-precision twin computes in: x87 extended precision
+ * (64-bit significand) on x86-64. */
+typedef long double ext_t;
+
+/* The same substitution carried in ext_t; xl holds the extended values, x
+ * the values rounded once to double at the end. */
 void oracle_solve_ld(int n, const int *row_ptr, const int *col_idx,
                      const double *val, const double *b, double *x)
 {
-    long double *xl = (long double *)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    ext_t *xl = (ext_t *)malloc(sizeof(ext_t) * (size_t)(n > 0 ? n : 1));
     for (int i = 0; i < n; ++i) {
-        long double s = 0.0L, d = 0.0L;
+        ext_t s = 0, d = 0;
         for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
             int j = col_idx[p];
             if (j < i)
-                s = s + (long double)val[p] * xl[j];
+                s = s + (ext_t)val[p] * xl[j];
             else
-                d = (long double)val[p];
+                d = (ext_t)val[p];
         }
-        xl[i] = ((long double)b[i] - s) / d;
+        xl[i] = ((ext_t)b[i] - s) / d;
         x[i] = (double)xl[i];
     }
     free(xl);

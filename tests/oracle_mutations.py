@@ -4,7 +4,8 @@ Plants one plausible mistake at a time in a copy of ``oracle/oracle.c`` (a
 dropped or flipped sign, a wrong index, an off-by-one test), builds the copy
 in a temporary directory and runs ``tests/test_oracle_pins.py`` against it
 through ``ORACLE_LIB``; likewise for the cost model's ``oracle/mlp.py`` (a
-copy of the package first on the path) against ``tests/test_oracle_mlp.py``.
+copy of the package first on the path) against ``tests/test_oracle_mlp.py``,
+and for the package's own Python (the FLOP count) against the pins.
 Every mutant must make at least one pin fail; the repository's own oracle is
 never touched.
 
@@ -30,8 +31,9 @@ MUTANTS = [
     ("stage depth test", r"candidate = width <= max_width && depth < max_depth;",
      "candidate = width <= max_width && depth <= max_depth;"),
     ("b index of a b-term", r"bi = bi \+ m_val\[p\] \* b\[m_col\[p\]\];", "bi = bi + m_val[p] * b[i];"),
-    ("sign in the long-double solve", r"s = s \+ \(long double\)val\[p\] \* xl\[j\];",
-     "s = s - (long double)val[p] * xl[j];"),
+    ("sign in the long-double solve", r"s = s \+ \(ext_t\)val\[p\] \* xl\[j\];",
+     "s = s - (ext_t)val[p] * xl[j];"),
+    ("extended solve carried in double", r"typedef long double ext_t;", "typedef double ext_t;"),
     ("diagonal test of the backward solve", r"if \(j > i\)\n", "if (j >= i)\n"),
     ("level-set counts shifted", r"level_ptr\[level\[i\] \+ 1\] \+= 1;", "level_ptr[level[i]] += 1;"),
     ("width rule < for <=", r"candidate = width <= max_width", "candidate = width < max_width"),
@@ -50,6 +52,14 @@ MLP_MUTANTS = [
     ("first-layer gradient transposed", r'"W1": d1\.T @ X', '"W1": (X.T @ d1).T.reshape(X.shape[1], -1).T'),
     ("Adam without bias correction", r"mh = m1 / \(1\.0 - beta1 \*\* step\)", "mh = m1"),
     ("output bias dropped", r"return h2 @ q\[\"w3\"\] \+ q\[\"b3\"\]\[0\]", "return h2 @ q[\"w3\"]"),
+]
+
+
+# mistakes in the oracle's Python side (oracle/__init__.py), checked by
+# tests/test_oracle_pins.py against a copy of the package placed first on the path
+INIT_MUTANTS = [
+    ("b-terms counted once in the FLOPs", r"return 2 \* \(off \+ nm\) \+ n", "return 2 * off + nm + n"),
+    ("divisions left out of the FLOPs", r"return 2 \* \(off \+ nm\) \+ n", "return 2 * (off + nm)"),
 ]
 
 
@@ -82,6 +92,24 @@ def main() -> int:
                 f.write(mutated)
             rc, msg = run_pins("test_oracle_mlp.py", {"PYTHONPATH": tmp + os.pathsep + ROOT, "ORACLE_LIB": lib_real},
                                cwd=tmp)
+            if rc == 0:
+                print(f"SURVIVED ({what})")
+                survived += 1
+            else:
+                print(f"killed ({what}): {msg}")
+        with open(os.path.join(pkg, "mlp.py"), "w") as f:
+            f.write(mlp_src)
+        init_src = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+        for what, pat, rep in INIT_MUTANTS:
+            mutated, count = re.subn(pat, rep, init_src, count=1)
+            if count != 1:
+                print(f"NOT APPLIED ({what}): pattern not found")
+                survived += 1
+                continue
+            with open(os.path.join(pkg, "__init__.py"), "w") as f:
+                f.write(mutated)
+            rc, msg = run_pins("test_oracle_pins.py", {"PYTHONPATH": tmp + os.pathsep + ROOT,
+                                                       "ORACLE_LIB": lib_real}, cwd=tmp)
             if rc == 0:
                 print(f"SURVIVED ({what})")
                 survived += 1

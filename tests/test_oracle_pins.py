@@ -362,9 +362,69 @@ def test_long_double_is_closer_to_exact():
         assert eld <= e64 or eld <= abs(ex[i]) * Fraction(2.0 ** -53)
 
 
-def test_flops_definition():
-    s = wl.stencil2d(10, seed=0)
-    assert oracle.flops(s.row_ptr) == 2 * (s.nnz - s.n) + s.n
+def _drifting_chain(n, seed):
+    """Unit lower bidiagonal L with sub-diagonal -a, a = 1 - 2^-20, and b in
+    [0.5, 1): x_i = b_i + a x_{i-1}.  Every step rounds a product and a sum,
+    and with a so close to 1 those errors are carried forward almost
+    undamped, so FP64 substitution drifts away from the exact solution."""
+    a = 1.0 - 2.0 ** -20
+    rng = np.random.default_rng(seed)
+    b = rng.uniform(0.5, 1.0, n)
+    rp = np.concatenate([[0], np.arange(1, n + 1) * 2 - 1]).astype(np.int32)
+    ci = np.empty(2 * n - 1, np.int32)
+    v = np.empty(2 * n - 1)
+    ci[0], v[0] = 0, 1.0
+    for i in range(1, n):
+        ci[2 * i - 1], v[2 * i - 1] = i - 1, -a
+        ci[2 * i], v[2 * i] = i, 1.0
+    exact, xa = [], Fraction(0)
+    for i in range(n):
+        xa = Fraction(float(b[i])) + Fraction(a) * xa
+        exact.append(xa)
+    return rp, ci, v, b, exact
+
+
+def _ulps(x, exact):
+    import math
+    return [abs(Fraction(float(xi)) - e) / Fraction(math.ulp(float(e))) for xi, e in zip(x, exact)]
+
+
+def test_long_double_solve_is_extended_precision():
+    """The extended-precision twin (the reference of the FP32 + refinement
+    gate) really carries more than 53 bits: on a chain where the FP64
+    substitution of Algorithm 1 drifts over ten ulps from the exact solution,
+    the twin, rounded once to FP64 at the end, stays within one ulp of the
+    exact solution at every component.  A twin that computed in double would
+    reproduce the FP64 drift and fail."""
+    rp, ci, v, b, exact = _drifting_chain(400, seed=7)
+    e64 = _ulps(oracle.solve(rp, ci, v, b), exact)
+    eld = _ulps(oracle.solve_ld(rp, ci, v, b), exact)
+    # the FP64 oracle demonstrably drifts on this system (the test has teeth)
+    assert max(e64) > 8 and sum(e > 4 for e in e64) > 100
+    # 64-bit significand: 400 steps add at most ~400 * 2^-64 relative before
+    # the final rounding's half ulp
+    assert max(eld) <= 1, max(eld)
+    # and it is strictly closer wherever FP64 is off by more than an ulp
+    assert all(l < d for l, d in zip(eld, e64) if d > 1)
+
+
+def test_flops_hand_counted_fig2():
+    """FLOPs of the plans of the Fig. 2 chain (rows 1, 2 depend on row 0,
+    row 3 on row 1), counted by hand: a multiply and an add per off-diagonal
+    x-term or b-term, one division per row.
+      L:      row 0: 1; rows 1-3: 2 + 1 each              = 10
+      step 1: row 3 holds x_0 and b_1: 2 + 2 + 1 = 5      = 12
+      step 2: rows 1, 2 hold b_0 (3 each), row 3 b_0, b_1 = 12"""
+    with open(os.path.join(GOLDEN, "fig2_chain.json")) as f:
+        g = json.load(f)
+    s = wl.from_pairs(g["n"], g["pairs"], seed=11)
+    assert oracle.flops(s.row_ptr) == 10
+    nlev = oracle.levels(s.row_ptr, s.col_idx)[1]
+    got = []
+    for step in g["steps"]:
+        p = oracle.plan(s.row_ptr, s.col_idx, s.val, _explicit(nlev, step["absorbed_levels"]))
+        got.append(oracle.flops(p["lp"][0], p["m"][0]))
+    assert got == [12, 12]
 
 
 # ------------------------------------------ backward substitution (U x = b) --
