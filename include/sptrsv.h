@@ -170,7 +170,9 @@ sptrsv_status sptrsv_device_bytes(sptrsv_plan plan, size_t *bytes);
 /* Copies the packed plan into dev_buf (device, >= sptrsv_device_bytes, owned
  * by the caller, 256-byte aligned, must stay allocated while the plan is
  * solved with) on stream, and waits for the copy to finish.  The plan
- * remembers dev_buf.  Errors: ARG (null, too small, misaligned), HIP. */
+ * remembers dev_buf.  Errors: ARG (null, too small, misaligned), HIP (also
+ * when a solve kernel was built with scratch memory, whose co-residency the
+ * cooperative launch cannot rely on). */
 sptrsv_status sptrsv_upload(sptrsv_plan plan, void *dev_buf, size_t bytes, void *stream);
 
 /* Solves L x = b (device arrays of n doubles, b != x, neither overlapping
@@ -268,9 +270,11 @@ sptrsv_status sptrsv_refine_stats(sptrsv_plan plan, void *stream, int32_t *itera
 sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_status);
 
 /* Launch shape of the solve: waves (one per workgroup, all co-resident) per
- * compute unit, capped by what the device can keep resident; 0 (the
- * default) picks 1..8 from the plan's tiles per level.  Takes effect at the
- * next solve.  Errors: ARG (negative). */
+ * compute unit, at most 8 (the co-residency the kernels' registers and LDS
+ * prove; every wave must be resident for the grid to drain) and capped by
+ * what the device reports it can keep resident; 0 (the default) picks 1..8
+ * from the plan's tiles per level.  Takes effect at the next solve.
+ * Errors: ARG (negative, or above 8). */
 sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu);
 
 /* Upper bound, in ticks of the 100 MHz GPU real-time clock, on a single

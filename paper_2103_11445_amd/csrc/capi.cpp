@@ -70,7 +70,7 @@ int launch_waves(const sptrsv::Plan &p) {
         if (p.comp_segs > 0)
             wpc = std::max<int>(wpc, (int)((p.comp_segs + std::max(1, p.cus) - 1) / std::max(1, p.cus)));
     }
-    wpc = std::min(wpc, p.max_waves_per_cu);
+    wpc = std::min({wpc, p.max_waves_per_cu, sptrsv::kMaxWavesPerCU});
     const int64_t w = std::min<int64_t>((int64_t)p.cus * wpc, p.ntiles);
     return (int)std::max<int64_t>(1, w);
 }
@@ -439,6 +439,8 @@ sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_statu
 sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu) {
     if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
     if (waves_per_cu < 0) return set_err(SPTRSV_ERR_ARG, "waves_per_cu < 0");
+    if (waves_per_cu > sptrsv::kMaxWavesPerCU)
+        return set_err(SPTRSV_ERR_ARG, "waves_per_cu above 8: co-residency of the grid is not proven there");
     plan->waves_per_cu = waves_per_cu;
     return SPTRSV_OK;
 }

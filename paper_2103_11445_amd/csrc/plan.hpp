@@ -29,6 +29,15 @@ constexpr int kStageSegTiles = 4; // a stage of a stage system is one segment if
 
 constexpr int kMaxRefine = 16;    // refinement iterations per call (slots in the workspace)
 
+// Most single-wave workgroups per CU the cooperative solve grid may use.
+// Every wave must be resident for the grid to drain (a wave that never
+// starts holds items others wait on), and 8 per CU is what the kernels'
+// resources prove: at most 256 VGPRs (2 waves per SIMD, 4 SIMDs) and a
+// 16,392-byte LDS ring, 8 of which fit in 160 KB of LDS even at a 2 KB
+// allocation granularity (9 would need a granularity below ~1.8 KB).  The
+// occupancy query can report more; it is capped here.
+constexpr int kMaxWavesPerCU = 8;
+
 // How the solve applies the rewritten right-hand side b' = b + M b.
 enum RhsMode : int32_t {
     kRhsNone = 0,   // no b-terms: the solve reads b

@@ -875,11 +875,17 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
                           reinterpret_cast<const void *>(solve_tiles<float, false, 8, true>),
                           reinterpret_cast<const void *>(solve_tiles<double, true, 4, false>),
                           reinterpret_cast<const void *>(solve_tiles<double, true, 8, false>)};
-    int most = INT32_MAX;
+    int most = sptrsv::kMaxWavesPerCU;
     for (const void *k : inst) {
         int b = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, 64, 0);
         if (e != hipSuccess) return (int)e;
+        // a kernel that spills to scratch may be held back by the scratch
+        // backing even where the occupancy query says it fits: refuse it
+        hipFuncAttributes fa;
+        e = hipFuncGetAttributes(&fa, k);
+        if (e != hipSuccess) return (int)e;
+        if (fa.localSizeBytes != 0) return (int)hipErrorInvalidKernelFile;
         most = std::min(most, b);
     }
     *max_waves_per_cu = most;

@@ -9,7 +9,9 @@ component, already exceeds 1e-10 (banded n=1e6: the oracle is 1.46e-10 from
 the extended-precision solution at x_i = -5.8e-8), so any computation with a
 different rounding order lands farther than that from it.  The gate
 therefore bounds the error relative to each component, floored at 1e-3 of
-the largest component; the strict figure is reported next to it.
+the largest component; the strict figure is reported next to it, and
+report() counts the components the floor touched and those that pass only
+because of it.
 """
 import numpy as np
 
@@ -33,3 +35,25 @@ def errors(x, ref):
 
 def ok(x, ref, tol=TOL) -> bool:
     return errors(x, ref)[1] <= tol
+
+
+def report(x, ref, tol=TOL) -> dict:
+    """Both errors, plus how often the floor mattered: components whose
+    reference is below the floor (their denominator was raised to it), and
+    components whose strict error exceeds tol (those pass only because of the
+    floor).  An empty reference reports zeros."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    strict, floored = errors(x, ref)
+    out = {"strict": strict, "floored": floored, "components": int(ref.size),
+           "floored_components": 0, "strict_over_tol": 0, "floored_over_tol": 0}
+    if ref.size == 0:
+        return out
+    d = np.abs(x - ref)
+    scale = FLOOR * float(np.max(np.abs(ref)))
+    out["floored_components"] = int(np.count_nonzero(np.abs(ref) < scale))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        out["strict_over_tol"] = int(np.count_nonzero(
+            ~(d / np.maximum(np.abs(ref), np.finfo(np.float64).tiny) <= tol)))
+        out["floored_over_tol"] = int(np.count_nonzero(~(d / np.maximum(np.abs(ref), scale) <= tol)))
+    return out

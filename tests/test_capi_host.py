@@ -95,6 +95,38 @@ def test_plan_bit_exact(sp, make, pol):
     compare_with_oracle(sp, make(), pol)
 
 
+# Every policy the benchmark's tuning leg can pick, on reduced instances of
+# the large workload's three families (sized so that the oracle's sorted-list
+# rewrite finishes in seconds): levels, stages, entries per level, L' and M
+# structure and values, levels of L' and the schedule, bit for bit.
+def _bench_policy(cand):
+    import bench
+    kind, kw = bench.CANDIDATES[cand]
+    return {"kind": kind, **kw}
+
+
+BENCH_CASES = [
+    # the thin-level rule: budget binding (long tail) and not binding (short tail)
+    ("powerlaw 2e5 tail 2e4", lambda: wl.powerlaw(200000, 20000, seed=3), ["paper", "paper256"]),
+    ("powerlaw 2e5 tail 1e3", lambda: wl.powerlaw(200000, 1000, seed=3), ["paper", "paper256"]),
+    ("powerlaw 2e4 tail 2e3", lambda: wl.powerlaw(20000, 2000, seed=3),
+     ["depth2", "depth16", "depth64", "depth128", "depth256", "depth512"]),
+    ("banded 2e4 bw 200", lambda: wl.banded(20000, 200, 8, 24, seed=2), ["depth2", "depth16", "depth64", "depth128"]),
+    ("banded 1e4 bw 200", lambda: wl.banded(10000, 200, 8, 24, seed=2), ["depth256", "depth512"]),
+    ("stencil3d 32", lambda: wl.stencil3d(32, seed=1),
+     ["paper", "paper256", "depth2", "depth16", "depth64", "depth128", "depth256", "depth512"]),
+]
+
+
+@pytest.mark.parametrize("name,make,cands", BENCH_CASES, ids=[c[0] for c in BENCH_CASES])
+def test_bench_policies_bit_exact(sp, name, make, cands):
+    s = make()
+    for cand in cands:
+        plan, o = compare_with_oracle(sp, s, _bench_policy(cand))
+        assert o["nlev_rw"] < o["nlev"] or cand == "plain", (name, cand)
+        plan.close()
+
+
 def test_explicit_masks_bit_exact(sp):
     rng = np.random.default_rng(3)
     s = wl.powerlaw(20000, 800, seed=9)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gate import TOL, errors
+from gate import TOL, errors, report
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -55,7 +55,7 @@ def test_large_tuned(torch, sp, bench, name):
         assert plan.check() == 0
         err = errors(x.cpu().numpy(), ref)
         info = plan.info()
-        print(name, label, info["levels_rw"], info["rhs_mode"], err, flush=True)
+        print(name, label, info["levels_rw"], info["rhs_mode"], report(x.cpu().numpy(), ref), flush=True)
         assert np.all(np.isfinite(x.cpu().numpy()))
         assert err[1] <= TOL
         plan.close()
