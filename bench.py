@@ -32,7 +32,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.join(ROOT, "tests"))
-from gate import TOL, errors  # noqa: E402  (floored componentwise error, see tests/gate.py)
+from gate import TOL, errors, report  # noqa: E402  (floored componentwise error, see tests/gate.py)
 
 HBM_PEAK_GBS = 8000.0
 LARGE = ["stencil3d_128", "banded_1m", "powerlaw_4m"]
@@ -110,6 +110,95 @@ def profiled_traffic():
             **{n: float(kv[f"traffic_bytes {n}"]) for n in LARGE if f"traffic_bytes {n}" in kv}}
 
 
+def cpu_host():
+    """(CPU model from lscpu, cores this process may run on, threads the
+    level-set leg uses: the cores, capped by OMP_NUM_THREADS when set)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(cores, int(omp)) if omp.isdigit() and int(omp) > 0 else cores
+    return model, cores, threads
+
+
+def percentiles(v):
+    v = np.asarray(v, dtype=np.float64)
+    return {"median": float(np.median(v)), "p10": float(np.percentile(v, 10)),
+            "p90": float(np.percentile(v, 90))}
+
+
+def stage_system(s, level, stage_of_level):
+    """The stages' diagonal blocks of L (entries whose two rows' levels share
+    a stage), as CSR: the system whose solve y gives b' = D y."""
+    stage = stage_of_level[level]
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    keep = stage[rows] == stage[s.col_idx]
+    rp = np.zeros(s.n + 1, dtype=np.int32)
+    np.cumsum(np.bincount(rows[keep], minlength=s.n), out=rp[1:])
+    return rp, s.col_idx[keep].astype(np.int32), s.val[keep]
+
+
+def cpu_levelset_leg(names, systems, plans, refs, threads, seconds):
+    """The level-set solve on the host cores (OpenMP, a barrier per level),
+    on the plain level sets of L and on the same rewritten plan the GPU runs:
+    L' with b' = b + M b (M pass), or b' = D y with L_B y = b (stage solve)."""
+    import oracle
+    forms = {}
+    for n in names:
+        s = systems[n]
+        lv, nlev = oracle.levels(s.row_ptr, s.col_idx)
+        ptr, rows = oracle.level_sets(lv, nlev)
+        plain_lp = (s.row_ptr.astype(np.int64), s.col_idx, s.val)
+        forms[(n, "plain")] = (lambda ptr=ptr, rows=rows, lp=plain_lp, b=s.b:
+                               oracle.solve_levelset(ptr, rows, lp, None, b, threads))
+        p = plans[n]
+        info = p.info()
+        sptr, srows = p.schedule()
+        stage_mode = info["rhs_mode"] == 2
+        lp, m = p.export(with_m=not stage_mode)
+        if stage_mode:
+            sol, _ = p.stages()
+            brp, bci, bval = stage_system(s, p.levels(0), sol)
+            blv, bnl = oracle.levels(brp, bci)
+            bptr, brows = oracle.level_sets(blv, bnl)
+            blp = (brp.astype(np.int64), bci, bval)
+            diag = s.val[s.row_ptr[1:] - 1]
+
+            def rewritten(sptr=sptr, srows=srows, lp=lp, b=s.b, bptr=bptr, brows=brows, blp=blp, diag=diag):
+                y = oracle.solve_levelset(bptr, brows, blp, None, b, threads)
+                return oracle.solve_levelset(sptr, srows, lp, None, diag * y, threads)
+            forms[(n, "rewritten")] = rewritten
+        else:
+            forms[(n, "rewritten")] = (lambda sptr=sptr, srows=srows, lp=lp, m=m, b=s.b:
+                                       oracle.solve_levelset(sptr, srows, lp, m, b, threads))
+    out = {}
+    for kind in ("plain", "rewritten"):
+        per, errs, count, t_total = {n: [] for n in names}, {}, 0, 0.0
+        while True:
+            for n in names:
+                t0 = time.perf_counter()
+                x = forms[(n, kind)]()
+                per[n].append(time.perf_counter() - t0)
+                if n in refs and n not in errs:
+                    errs[n] = errors(x, refs[n])[1]
+                count += 1
+            t_total = sum(sum(v) for v in per.values())
+            if t_total >= seconds / 2:
+                break
+        out[kind] = {"value": count / t_total, "unit": "solves/s",
+                     "ms_per_solve": {n: 1e3 * float(np.median(v)) for n, v in per.items()},
+                     "solves": count, "max_rel_err_floored": errs}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,9 +207,12 @@ def main():
     ap.add_argument("--workload", choices=["large", "small", "batched", "precision"], default="large")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU leg (and the parity check)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU legs (and the parity check)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--flush-mb", type=int, default=0, metavar="MB",
+                    help="counter runs only: copy MB of device memory before every solve of the timed "
+                         "leg (evicts the 256 MB Infinity Cache); no throughput is reported")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
@@ -167,7 +259,8 @@ def main():
 
     # ---- CPU leg: the oracle, timed on the host; its x are the references
     refs, cpu = {}, None
-    if not args.no_cpu:
+    cpu_model, cpu_cores, cpu_threads = cpu_host()
+    if not args.no_cpu and not args.flush_mb:
         import oracle
         t_total, count = 0.0, 0
         t0 = time.perf_counter()
@@ -182,7 +275,8 @@ def main():
         cpu = {"value": count / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
                "sample": f"serial FP64 forward substitution (the oracle) over the same "
                          f"{len(names)} systems, cycled {count // len(names)} times in {t_total:.1f} s "
-                         f"on one host core"}
+                         f"on one host core",
+               "cpu_model": cpu_model}
         log(f"[cpu] {cpu}")
 
     def make_plan(name, cand):
@@ -213,7 +307,7 @@ def main():
     # ---- tuning leg
     plans, chosen, tuning, tiling, waves = {}, {}, {}, {}, {}
     for n in names:
-        if args.no_tune:
+        if args.no_tune or args.flush_mb:
             chosen[n] = TUNED.get(n, "paper")
             tiling[n] = TUNED_TILING.get(n, 4)
             waves[n] = TUNED_WAVES.get(n, 0)
@@ -285,17 +379,39 @@ def main():
                 best_ms, waves[n] = ms, wpc
         plans[n].set_launch(waves[n])
 
+    if args.flush_mb:
+        # counter runs: every solve starts with the Infinity Cache evicted
+        fsrc = torch.ones(args.flush_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        fdst = torch.empty_like(fsrc)
+        per = {n: [] for n in names}
+        for _ in range(args.steps):
+            for n in names:
+                fdst.copy_(fsrc)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                plans[n].solve(bs[n], xs[n])
+                b.record(stream)
+                per[n].append((a, b))
+        torch.cuda.synchronize()
+        out = {"flush_mb": args.flush_mb, "steps": args.steps,
+               "ms_per_solve": {n: float(np.mean([a.elapsed_time(b) for a, b in per[n]])) for n in names},
+               "status": {n: plans[n].check() for n in names}}
+        for p in plans.values():
+            p.close()
+        torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
+        return
+
     # ---- timed leg
     def run(plan_set, steps, tag):
         for _ in range(args.warmup):
             for n in names:
                 plan_set[n].solve(bs[n], xs[n])
         torch.cuda.synchronize()
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         ev = {n: [] for n in names}
-        start.record(stream)
-        for _ in range(steps):
+        marks[0].record(stream)
+        for k in range(steps):
             for n in names:
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
@@ -303,23 +419,37 @@ def main():
                 plan_set[n].solve(bs[n], xs[n])
                 b.record(stream)
                 ev[n].append((a, b))
-        end.record(stream)
+            marks[k + 1].record(stream)
         torch.cuda.synchronize()
-        total_ms = start.elapsed_time(end)
-        per = {n: float(np.mean([a.elapsed_time(b) for a, b in ev[n]])) for n in names}
+        total_ms = marks[0].elapsed_time(marks[-1])
+        step_ms = [marks[k].elapsed_time(marks[k + 1]) for k in range(steps)]
+        solve_ms = {n: [a.elapsed_time(b) for a, b in ev[n]] for n in names}
+        per = {n: float(np.mean(v)) for n, v in solve_ms.items()}
         status = {n: plan_set[n].check() for n in names}
-        errs = {n: errors(xs[n].cpu().numpy(), refs[n]) if n in refs else None for n in names}
+        reps = {n: report(xs[n].cpu().numpy(), refs[n]) if n in refs else None for n in names}
+        errs = {n: None if r is None else (r["strict"], r["floored"]) for n, r in reps.items()}
         log(f"[{tag}] {steps} steps, {total_ms / steps:.3f} ms/step, per solve (ms) "
             f"{ {n: round(v, 4) for n, v in per.items()} }, (strict, floored) error {errs}, "
             f"status {status}")
-        return total_ms, per, errs, status
+        return total_ms, per, errs, status, step_ms, solve_ms, reps
 
     log("[timed] tuned plans")
-    total_ms, per, errs, status = run(plans, args.steps, "timed")
-    plain_res = None
+    total_ms, per, errs, status, step_ms, solve_ms, reps = run(plans, args.steps, "timed")
+    plain_res, plain = None, {}
     if not args.no_plain:
         plain = {n: make_plan(n, "plain")[0] for n in names}
         plain_res = run(plain, args.plain_steps, "plain")
+
+    # ---- dependency-latency bound: one hop per executed level, the hop
+    # measured here (device-scope publish seen by a poll on another XCD)
+    hop_ns = {"cross_xcd": sp.probe_hop(20000, same_xcd=False), "same_xcd": sp.probe_hop(20000, same_xcd=True)}
+    log(f"[hop] {hop_ns}")
+
+    # ---- CPU level-set leg on all host cores, plain and rewritten
+    cpu_ls = None
+    if refs:
+        cpu_ls = cpu_levelset_leg(names, systems, plans, refs, cpu_threads, args.cpu_seconds)
+        log(f"[cpu levelset] {cpu_threads} threads: {cpu_ls}")
 
     ms_per_step = total_ms / args.steps
     nsolve = len(names)
@@ -327,21 +457,24 @@ def main():
     matrices = {}
     for n in names:
         i = plans[n].info()
+        bound_us = i["levels_rw"] * hop_ns["cross_xcd"] * 1e-3
         m = {
             "n": i["n"], "nnz": i["nnz"], "levels": i["levels"], "stages": i["stages"],
             "levels_rw": i["levels_rw"], "entries_rw": i["nnz_rw"] + i["nnz_m"],
             "flops": i["flops"], "flops_rw": i["flops_rw"], "bytes": i["bytes"],
             "bytes_rw": i["bytes_rw"], "policy": chosen[n], "terms_per_lane": tiling[n],
             "waves_per_cu": waves[n],
-            "rhs_mode": i["rhs_mode"], "ms_per_solve": per[n],
+            "rhs_mode": i["rhs_mode"], "ms_per_solve": per[n], "ms_per_solve_pct": percentiles(solve_ms[n]),
             "solves_per_s": 1000.0 / per[n],
             "plan_gbps": i["bytes_rw"] / (per[n] * 1e-3) / 1e9,
             "effective_gbps": i["bytes"] / (per[n] * 1e-3) / 1e9,
             "us_per_level": 1000.0 * per[n] / max(1, i["levels_rw"]),
+            "latency_bound_us": bound_us, "latency_frac": bound_us / (1000.0 * per[n]),
             "device_status": status[n], **{k: round(v, 3) for k, v in host[n].items()},
         }
-        if errs[n] is not None:
+        if reps[n] is not None:
             m["max_rel_err_strict"], m["max_rel_err_floored"] = errs[n]
+            m["error"] = reps[n]
         if plain_res is not None:
             m["plain_ms_per_solve"] = plain_res[1][n]
             m["speedup_vs_plain"] = plain_res[1][n] / per[n]
@@ -357,11 +490,13 @@ def main():
         if plain_res is not None:
             parity = parity and all(e[1] <= TOL for e in plain_res[2].values()) \
                 and not any(plain_res[3].values())
-    # roofline of the solve kernel: algorithmic bytes of the rewritten plans
-    # over the time of their solves (fill kernel included: it is part of
-    # every solve), against the 8 TB/s HBM peak
+    # roofline of the solve call (its kernels: the right-hand-side step and
+    # the dependent solve): algorithmic bytes of the rewritten plans over the
+    # time of their solve calls, against the 8 TB/s HBM peak; the effective
+    # figure counts only the plain system's bytes (the useful work of Lx=b)
     kern_ms = sum(per.values())
     achieved = sum(plans[n].info()["bytes_rw"] for n in names) / (kern_ms * 1e-3) / 1e9
+    effective = sum(plans[n].info()["bytes"] for n in names) / (kern_ms * 1e-3) / 1e9
     # measured HBM bytes (rocprofv3 counters, calibrated) of the same kernel,
     # plans and workload; only valid for the tuned policies it was taken with
     traffic = None
@@ -374,7 +509,8 @@ def main():
     out = {
         "metric": "SpTRSV solves/s + achieved HBM GB/s vs plain level-set, rel err <=1e-10",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "ms_per_step_pct": percentiles(step_ms),
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": ("stencil3d_128 + banded_1m + powerlaw_4m, FP64 CSR int32, 1 RHS"
                                 if args.workload == "large" else "stencil2d_100, FP64 CSR int32, 1 RHS"),
@@ -382,8 +518,16 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      # per launch like "achieved": the step's three launches averaged
-                     "traffic": None if traffic is None else traffic["step"] / len(names)},
+                     "traffic": None if traffic is None else traffic["step"] / len(names),
+                     "effective_achieved": effective, "effective_frac": effective / HBM_PEAK_GBS},
+        "latency": {"hop_ns": hop_ns,
+                    "bound_ms_per_step": sum(m["latency_bound_us"] for m in matrices.values()) * 1e-3,
+                    "frac": sum(m["latency_bound_us"] for m in matrices.values()) * 1e-3 / ms_per_step},
         "cpu_baseline": cpu,
+        "cpu_levelset": None if cpu_ls is None else {
+            "value": cpu_ls["rewritten"]["value"], "unit": "solves/s", "cores": cpu_threads,
+            "host_cores": cpu_cores, "cpu_model": cpu_model, "kind": "levelset (OpenMP, barrier per level)",
+            "plain": cpu_ls["plain"], "rewritten": cpu_ls["rewritten"]},
         "parity_ok": parity,
         "plain_levelset": None if plain_res is None else {
             "solves_per_s": nsolve * 1000.0 * args.plain_steps / plain_res[0],
@@ -391,6 +535,12 @@ def main():
         },
         "matrices": matrices,
     }
+    # release the plans and device buffers before the interpreter tears
+    # down (graphs, streams and buffers freed while the runtime still runs)
+    for p in list(plans.values()) + list(plain.values()):
+        p.close()
+    del bs, xs
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     if parity is False:
         sys.exit(1)
@@ -512,6 +662,10 @@ def bench_batched(args, torch, sp, workloads, stream):
         "speedup_vs_plain": None if plain_ms is None else plain_ms / ms,
         "tuning_ms": grid,
     }
+    plan.close()
+    for p_, _, _ in (plains if not args.no_plain else []):
+        p_.close()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     if out["parity_ok"] is False:
         sys.exit(1)
@@ -621,6 +775,8 @@ def bench_precision(args, torch, sp, workloads, stream):
         "legs": res,
         "speedup_vs_plain_fp64": plain_ms / ms,
     }
+    plan.close()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     if out["parity_ok"] is False:
         sys.exit(1)

@@ -344,7 +344,8 @@ sptrsv_status sptrsv_plan_schedule(sptrsv_plan plan, int32_t *level_ptr, int32_t
 /* The rewritten system as CSR (host arrays sized by sptrsv_plan_info):
  * L' = (lp_ptr int64[n+1], lp_col int32[nnz_rw], lp_val double[nnz_rw]) with
  * ascending columns and the diagonal last, and M = (m_ptr int64[n+1],
- * m_col int32[nnz_m], m_val double[nnz_m]) with ascending columns. */
+ * m_col int32[nnz_m], m_val double[nnz_m]) with ascending columns.  With
+ * m_ptr NULL only L' is written (M can be far larger).  Errors: ARG. */
 sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_col,
                                  double *lp_val, int64_t *m_ptr, int32_t *m_col,
                                  double *m_val);
@@ -408,6 +409,22 @@ sptrsv_status sptrsv_mlp_grad(const float *params, const float *x, const float *
  * the step number for the bias corrections.  Errors: ARG, HIP. */
 sptrsv_status sptrsv_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step,
                               float lr, float beta1, float beta2, float eps, void *stream);
+
+/* ---- Diagnostics ----------------------------------------------------------
+ *
+ * Latency of one dependency hop as the solve sees it (the other bound of a
+ * level-scheduled solve, next to memory bandwidth: a solve of a schedule
+ * with L levels takes at least L hops).  Two waves on two compute units take
+ * `hops` turns (2 .. 2^24), each publishing a counter with a device-scope
+ * store and polling for the other's with device-scope loads, like a row
+ * published by one wave and gathered by another.  same_xcd != 0 puts the
+ * partner on the same XCD (workgroups 0 and 8), else on the next one (0 and
+ * 1), given the in-turn dispatch of workgroups to XCDs.  dev_scratch: device,
+ * >= 32 bytes, 8-byte aligned, owned by the caller.  Waits for stream, then
+ * writes the mean nanoseconds per hop.  Errors: ARG, HIP, TIMEOUT (a wait
+ * passed 100 ms). */
+sptrsv_status sptrsv_probe_hop(int32_t hops, int32_t same_xcd, void *dev_scratch, size_t bytes,
+                               double *ns_per_hop, void *stream);
 
 /* Releases the plan (host memory only; the caller frees its device buffer
  * after the last solve that uses it has finished).  NULL is ignored. */

@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     """Compile ``liboracle.so`` next to the source with gcc."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC",
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC",
                         "-shared", _SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -60,6 +60,7 @@ def _load():
             "oracle_rewrite_count": (None, [I, P, P, P, I, P, P, P]),
             "oracle_rewrite": (I, [I, P, P, P, P, I, P, P, P, P, P, P, P]),
             "oracle_solve_rewritten": (None, [I, P, P, P, P, P, P, P, P]),
+            "oracle_solve_levelset": (None, [I, P, P, I, P, P, P, P, P, P, P, P, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -211,6 +212,28 @@ def solve_rewritten(lp, m, b) -> np.ndarray:
     x = np.empty(n, dtype=np.float64)
     _load().oracle_solve_rewritten(n, _p(lp_ptr), _p(lp_col), _p(lp_val),
                                    _p(m_ptr), _p(m_col), _p(m_val), _p(b), _p(x))
+    return x
+
+
+def solve_levelset(level_ptr, rows, lp, m, b, threads: int = 1) -> np.ndarray:
+    """Level-set solve of L' x = b + M b on ``threads`` host cores (OpenMP,
+    a barrier between levels; Sec. II), over the level sets (level_ptr, rows)
+    of L'.  ``m=None`` for a plain system."""
+    level_ptr = np.ascontiguousarray(level_ptr, dtype=np.int32)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    lp_ptr = np.ascontiguousarray(lp[0], dtype=np.int64)
+    lp_col = np.ascontiguousarray(lp[1], dtype=np.int32)
+    lp_val = np.ascontiguousarray(lp[2], dtype=np.float64)
+    n = lp_ptr.size - 1
+    if m is None:
+        m = (np.zeros(n + 1, np.int64), np.zeros(1, np.int32), np.zeros(1, np.float64))
+    m_ptr = np.ascontiguousarray(m[0], dtype=np.int64)
+    m_col = np.ascontiguousarray(m[1], dtype=np.int32)
+    m_val = np.ascontiguousarray(m[2], dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.empty(n, dtype=np.float64)
+    _load().oracle_solve_levelset(n, _p(level_ptr), _p(rows), level_ptr.size - 1, _p(lp_ptr), _p(lp_col),
+                                  _p(lp_val), _p(m_ptr), _p(m_col), _p(m_val), _p(b), _p(x), int(threads))
     return x
 
 

@@ -8,9 +8,9 @@
  * benchmark's CPU-baseline leg may load this library.  It shares no source
  * with the GPU library and must never be on the product path.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared oracle.c -o liboracle.so
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -fPIC -shared oracle.c -o liboracle.so
  * (-ffp-contract=off: every a*b+c below is a rounded product followed by a
- *  rounded sum, exactly as written).
+ *  rounded sum, exactly as written; OpenMP only for the level-set solve).
  *
  * Input format (all functions): L is n x n lower triangular in CSR,
  *   row_ptr int32[n+1], col_idx int32[nnz], val double[nnz];
@@ -458,5 +458,41 @@ void oracle_solve_rewritten(int n, const int64_t *lp_ptr, const int *lp_col,
                 d = lp_val[p];
         }
         x[i] = (bi - s) / d;
+    }
+}
+
+/* Level-set execution on the host (Sec. II: the rows of one level do not
+ * depend on each other, so they run in parallel, and a barrier separates
+ * consecutive levels), with OpenMP on `threads` cores: the CPU comparator
+ * of the GPU solve.  It runs a rewritten system L' x = b + M b (Sec. III,
+ * Fig. 3) over the level sets of L' (level_ptr int32[nlev+1], rows
+ * int32[n]); a plain system is L' = L with an empty M.  Every row is
+ * computed exactly as in oracle_solve_rewritten, so the result is
+ * bit-identical to it whatever the thread count. */
+void oracle_solve_levelset(int n, const int *level_ptr, const int *rows, int nlev,
+                           const int64_t *lp_ptr, const int *lp_col, const double *lp_val,
+                           const int64_t *m_ptr, const int *m_col, const double *m_val,
+                           const double *b, double *x, int threads)
+{
+    (void)n;
+#pragma omp parallel num_threads(threads > 0 ? threads : 1)
+    for (int l = 0; l < nlev; ++l) {
+        /* the implicit barrier at the end of the loop is the level barrier */
+#pragma omp for schedule(static)
+        for (int q = level_ptr[l]; q < level_ptr[l + 1]; ++q) {
+            int i = rows[q];
+            double bi = b[i];
+            for (int64_t p = m_ptr[i]; p < m_ptr[i + 1]; ++p)
+                bi = bi + m_val[p] * b[m_col[p]];
+            double s = 0.0, d = 0.0;
+            for (int64_t p = lp_ptr[i]; p < lp_ptr[i + 1]; ++p) {
+                int k = lp_col[p];
+                if (k < i)
+                    s = s + lp_val[p] * x[k];
+                else
+                    d = lp_val[p];
+            }
+            x[i] = (bi - s) / d;
+        }
     }
 }

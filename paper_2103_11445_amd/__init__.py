@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 __all__ = ["Plan", "Policy", "SptrsvError", "library_path", "load", "STATUS", "mlp_forward",
-           "mlp_grad", "mlp_adam"]
+           "mlp_grad", "mlp_adam", "probe_hop"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
@@ -110,6 +110,7 @@ def load():
         "sptrsv_plan_stages": (S, [P, P, P]),
         "sptrsv_plan_schedule": (S, [P, P, P]),
         "sptrsv_plan_export": (S, [P, P, P, P, P, P, P]),
+        "sptrsv_probe_hop": (S, [I32, I32, P, ctypes.c_size_t, P, P]),
         "sptrsv_plan_destroy": (None, [P]),
         "sptrsv_last_error": (ctypes.c_char_p, []),
     }
@@ -226,14 +227,15 @@ class Plan:
         _check(load().sptrsv_plan_schedule(self._h, _ptr(ptr), _ptr(rows)))
         return ptr, rows
 
-    def export(self):
+    def export(self, with_m: bool = True):
+        """(L', M) as CSR triples; M is None with ``with_m=False``."""
         i = self.info()
         lp = (np.empty(self.n + 1, np.int64), np.empty(i["nnz_rw"], np.int32),
               np.empty(i["nnz_rw"], np.float64))
         m = (np.empty(self.n + 1, np.int64), np.empty(i["nnz_m"], np.int32),
-             np.empty(i["nnz_m"], np.float64))
+             np.empty(i["nnz_m"], np.float64)) if with_m else (None, None, None)
         _check(load().sptrsv_plan_export(self._h, *(_ptr(a) for a in lp), *(_ptr(a) for a in m)))
-        return lp, m
+        return lp, (m if with_m else None)
 
     def set_launch(self, waves_per_cu: int = 0):
         _check(load().sptrsv_set_launch(self._h, int(waves_per_cu)))
@@ -345,6 +347,18 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def probe_hop(hops: int = 20000, same_xcd: bool = False, scratch=None, stream=None) -> float:
+    """Mean nanoseconds of one dependency hop (device-scope publish seen by a
+    device-scope poll on another compute unit)."""
+    import torch
+    if scratch is None:
+        scratch = torch.zeros(8, dtype=torch.int64, device="cuda")
+    ns = ctypes.c_double()
+    _check(load().sptrsv_probe_hop(int(hops), int(bool(same_xcd)), _ptr(scratch), scratch.numel() * 8,
+                                   ctypes.byref(ns), _stream(stream)))
+    return ns.value
 
 
 # ------------------------------------------------------------- cost model --

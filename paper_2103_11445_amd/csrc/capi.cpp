@@ -508,13 +508,14 @@ sptrsv_status sptrsv_plan_schedule(sptrsv_plan plan, int32_t *level_ptr, int32_t
 
 sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_col, double *lp_val,
                                  int64_t *m_ptr, int32_t *m_col, double *m_val) {
-    if (!plan || !lp_ptr || !m_ptr) return set_err(SPTRSV_ERR_ARG, "null argument");
+    if (!plan || !lp_ptr) return set_err(SPTRSV_ERR_ARG, "null argument");
     const sptrsv::Plan &p = *plan;
     if ((!lp_col || !lp_val) && !p.lp_col.empty()) return set_err(SPTRSV_ERR_ARG, "null L' arrays");
-    if ((!m_col || !m_val) && !p.m_col.empty()) return set_err(SPTRSV_ERR_ARG, "null M arrays");
     std::copy(p.lp_ptr.begin(), p.lp_ptr.end(), lp_ptr);
     std::copy(p.lp_col.begin(), p.lp_col.end(), lp_col);
     std::copy(p.lp_val.begin(), p.lp_val.end(), lp_val);
+    if (!m_ptr) return SPTRSV_OK;  // L' only
+    if ((!m_col || !m_val) && !p.m_col.empty()) return set_err(SPTRSV_ERR_ARG, "null M arrays");
     std::copy(p.m_ptr.begin(), p.m_ptr.end(), m_ptr);
     std::copy(p.m_col.begin(), p.m_col.end(), m_col);
     std::copy(p.m_val.begin(), p.m_val.end(), m_val);
@@ -599,6 +600,30 @@ sptrsv_status sptrsv_mlp_adam(float *params, const float *grad, float *m1, float
     const int e = sptrsv_launch_mlp_adam(params, grad, m1, m2, step, lr, beta1, beta2, eps, stream);
     if (e != 0) return hip_err((hipError_t)e, "kernel launch");
     return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_probe_hop(int32_t hops, int32_t same_xcd, void *dev_scratch, size_t bytes,
+                               double *ns_per_hop, void *stream) {
+    return guarded([&]() -> sptrsv_status {
+        if (!dev_scratch || !ns_per_hop) return set_err(SPTRSV_ERR_ARG, "null argument");
+        if (bytes < 32) return set_err(SPTRSV_ERR_ARG, "scratch smaller than 32 bytes");
+        if (reinterpret_cast<uintptr_t>(dev_scratch) % 8 != 0)
+            return set_err(SPTRSV_ERR_ARG, "scratch not 8-byte aligned");
+        if (hops < 2 || hops > (1 << 24)) return set_err(SPTRSV_ERR_ARG, "hops must be in [2, 2^24]");
+        const int partner = same_xcd ? 8 : 1;
+        // 100 ms per wait at 100 MHz: far above any hop, so only a lost
+        // partner ends the probe early
+        int e = sptrsv_launch_hop_probe(dev_scratch, hops, partner, 10000000ull, stream);
+        if (e != 0) return hip_err((hipError_t)e, "hop probe launch");
+        hipError_t he = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (he != hipSuccess) return hip_err(he, "hipStreamSynchronize");
+        unsigned long long out[2] = {0, 0};
+        he = hipMemcpy(out, static_cast<unsigned long long *>(dev_scratch) + 2, sizeof(out), hipMemcpyDeviceToHost);
+        if (he != hipSuccess) return hip_err(he, "hipMemcpy");
+        if (out[1]) return set_err(SPTRSV_ERR_TIMEOUT, "hop probe: a wait passed its limit");
+        *ns_per_hop = (double)out[0] * 10.0 / hops;  // 100 MHz ticks
+        return SPTRSV_OK;
+    });
 }
 
 void sptrsv_plan_destroy(sptrsv_plan plan) { delete plan; }

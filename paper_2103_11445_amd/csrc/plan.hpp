@@ -225,3 +225,6 @@ extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Lay
                                      uint64_t wait_limit, const double *b, double *x, int iterations,
                                      double tol, void *stream);
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu);
+// hop latency probe: scratch = 4 device uint64 (flag, unused, ticks, failed)
+extern "C" int sptrsv_launch_hop_probe(void *scratch, int hops, int partner, unsigned long long limit,
+                                       void *stream);

@@ -856,7 +856,55 @@ hipError_t solve_once(const unsigned char *dev, const sptrsv::Layout *lay, int32
     return launch_tiles<T, kStamp>(a, waves, lay, s);
 }
 
+// ------------------------------------------------------------ hop probe --
+//
+// Latency of one dependency hop as the solve sees it: one lane of workgroup
+// 0 and one of workgroup `partner` take turns, each publishing a counter with
+// a device-scope store and polling for the other's answer with device-scope
+// loads (the solve's publish / wait pair).  Workgroup 0 times `hops` turns
+// with the real-time clock.  Workgroups are dispatched to the eight XCDs in
+// turn, so partner 1 sits on another XCD and partner 8 on the same one.  A
+// wait longer than `limit` ticks ends the probe and flags it in out[1].
+__global__ void __launch_bounds__(64) hop_probe(unsigned long long *flag, int hops, int partner,
+                                                unsigned long long limit, unsigned long long *out) {
+    const int b = blockIdx.x;
+    if ((b != 0 && b != partner) || threadIdx.x != 0) return;
+    const int mine = b == 0 ? 0 : 1;  // turns h with h % 2 == mine are this side's stores
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    unsigned long long failed = 0;
+    for (int h = 0; h < hops && !failed; ++h) {
+        const unsigned long long want = (unsigned long long)h + 1;
+        if ((h & 1) == mine) {
+            __hip_atomic_store(flag, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
+        const unsigned long long w0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+            if (__builtin_amdgcn_s_memrealtime() - w0 > limit) {
+                failed = 1;
+                break;
+            }
+        }
+    }
+    if (b == 0) {
+        out[0] = __builtin_amdgcn_s_memrealtime() - t0;
+        out[1] = failed;
+    }
+}
+
 }  // namespace
+
+extern "C" int sptrsv_launch_hop_probe(void *scratch, int hops, int partner, unsigned long long limit,
+                                       void *stream) {
+    unsigned long long *w = static_cast<unsigned long long *>(scratch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemsetAsync(w, 0, 4 * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return (int)e;
+    unsigned long long *flag = w, *out = w + 2;
+    void *args[] = {&flag, &hops, &partner, &limit, &out};
+    return (int)hipLaunchCooperativeKernel(reinterpret_cast<const void *>(hop_probe), dim3(partner + 1), dim3(64),
+                                           args, 0, s);
+}
 
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
     int dev = 0;

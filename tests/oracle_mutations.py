@@ -40,6 +40,11 @@ MUTANTS = [
     ("fill budget < for <=", r"take = added \+ delta <= budget", "take = added + delta < budget"),
     ("b-terms left out of a level's entries", r"delta \+= nx \+ nb - ", "delta += nx - "),
     ("sign in the rewritten solve", r"s = s \+ lp_val\[p\] \* x\[k\];", "s = s - lp_val[p] * x[k];"),
+    ("level-set solve skips the last level",
+     r"for \(int l = 0; l < nlev; \+\+l\) \{\n(\s*)/\* the implicit barrier",
+     "for (int l = 0; l + 1 < nlev; ++l) {\n\\1/* the implicit barrier"),
+    ("b-terms dropped in the level-set solve", r"(double bi = b\[i\];\n(\s*)for \(int64_t p = m_ptr\[i\]; p < m_ptr\[i \+ 1\]; \+\+p\)\n\s*bi = bi \+ m_val\[p\] \* b\[m_col\[p\]\];)(?![\s\S]*oracle_solve_rewritten)",
+     "double bi = b[i];"),
 ]
 
 
@@ -125,8 +130,8 @@ def main() -> int:
             lib = os.path.join(tmp, "liboracle.so")
             with open(c, "w") as f:
                 f.write(mutated)
-            subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", c, "-o", lib,
-                            "-lm"], check=True)
+            subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", c,
+                            "-o", lib, "-lm"], check=True)
             rc, msg = run_pins("test_oracle_pins.py", {"ORACLE_LIB": lib})
             if rc == 0:
                 print(f"SURVIVED ({what})")

@@ -450,3 +450,28 @@ def test_solve_upper_suffix_sums():
     U = wl.transpose(wl.System("bd", rp, ci, v, b))
     x = oracle.solve_upper(U.row_ptr, U.col_idx, U.val, b)
     assert np.array_equal(x, np.cumsum(b[::-1])[::-1])
+
+
+# ------------------------------------- level-set execution on host cores --
+
+@pytest.mark.parametrize("make,pol", [
+    (lambda: wl.stencil2d(40, seed=0), {"kind": "none"}),
+    (lambda: wl.stencil2d(40, seed=0), {"kind": "threshold", "max_width": 10**9, "max_depth": 4, "max_fill": 10.0}),
+    (lambda: wl.powerlaw(20000, 1500, seed=3), {"kind": "threshold", "max_width": 4, "max_depth": 64,
+                                                "max_fill": 1.0}),
+    (lambda: wl.banded(3000, 200, 8, 24, seed=2), {"kind": "threshold", "max_width": 10**9, "max_depth": 16,
+                                                   "max_fill": 20.0}),
+])
+def test_levelset_solve_matches_serial(make, pol):
+    """Sec. II: rows of a level are independent, so the level-set execution
+    (a barrier between levels, rows of a level on several threads) gives the
+    serial result bit for bit, on the plain system (against Algorithm 1) and
+    on rewritten ones (against the serial rewritten solve)."""
+    s = make()
+    p = oracle.plan(s.row_ptr, s.col_idx, s.val, pol)
+    ref = oracle.solve_rewritten(p["lp"], p["m"], s.b)
+    if pol["kind"] == "none":
+        assert np.array_equal(ref, oracle.solve(s.row_ptr, s.col_idx, s.val, s.b))
+    for threads in (1, 4):
+        x = oracle.solve_levelset(p["sched_ptr"], p["sched_rows"], p["lp"], p["m"], s.b, threads=threads)
+        assert np.array_equal(x, ref), threads
