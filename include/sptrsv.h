@@ -404,6 +404,20 @@ sptrsv_status sptrsv_mlp_grad(const float *params, const float *x, const float *
                               float *grad, float *loss, void *workspace, size_t workspace_bytes,
                               void *stream);
 
+/* As sptrsv_mlp_grad, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the workspace is a file-scope device array of the library,
+ * sized for m <= SPTRSV_MLP_NOALLOC_MAX_SAMPLES (about 8.6 MB, held on every
+ * GPU the library runs on until the process ends), so the call makes no
+ * allocation.  Results equal sptrsv_mlp_grad's bit for bit (same kernels,
+ * same summation order).  All calls on one GPU share the array: calls that
+ * overlap on one GPU (on different streams or threads) race and must not be
+ * issued.  The array's device address is looked up on the first call on
+ * each device.  Errors: ARG (m < 1, m above the maximum, null), HIP. */
+#define SPTRSV_MLP_NOALLOC_MAX_SAMPLES 8192
+sptrsv_status sptrsv_mlp_grad_noalloc(const float *params, const float *x, const float *t, int32_t m,
+                                      float *grad, float *loss, void *stream);
+
 /* One Adam step (Kingma and Ba, 2015) on params with moment buffers m1, m2
  * (device, SPTRSV_MLP_PARAMS floats each, zero before step 1); step >= 1 is
  * the step number for the bias corrections.  Errors: ARG, HIP. */

@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 __all__ = ["Plan", "Policy", "SptrsvError", "library_path", "load", "STATUS", "mlp_forward",
-           "mlp_grad", "mlp_adam", "probe_hop"]
+           "mlp_grad", "mlp_grad_noalloc", "mlp_adam", "probe_hop"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
@@ -100,6 +100,7 @@ def load():
         "sptrsv_mlp_forward": (S, [P, P, P, I32, P]),
         "sptrsv_mlp_grad_workspace": (S, [I32, P]),
         "sptrsv_mlp_grad": (S, [P, P, P, I32, P, P, P, ctypes.c_size_t, P]),
+        "sptrsv_mlp_grad_noalloc": (S, [P, P, P, I32, P, P, P]),
         "sptrsv_mlp_adam": (S, [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, P]),
         "sptrsv_check": (S, [P, P, P]),
@@ -388,6 +389,24 @@ def mlp_grad(params, x, t, grad=None, loss=None, workspace=None, stream=None):
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
     _check(load().sptrsv_mlp_grad(_ptr(params), _ptr(x), _ptr(t), m, _ptr(grad), _ptr(loss),
                                   _ptr(workspace), workspace.numel(), _stream(stream)))
+    return grad, loss
+
+
+MLP_NOALLOC_MAX_SAMPLES = 8192
+
+
+def mlp_grad_noalloc(params, x, t, grad=None, loss=None, stream=None):
+    """As :func:`mlp_grad` with the library's static device workspace (no
+    allocation by the library; at most MLP_NOALLOC_MAX_SAMPLES samples).
+    ``grad`` and ``loss`` are allocated here only when not given."""
+    import torch
+    m = int(x.shape[0])
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(load().sptrsv_mlp_grad_noalloc(_ptr(params), _ptr(x), _ptr(t), m, _ptr(grad), _ptr(loss),
+                                          _stream(stream)))
     return grad, loss
 
 

@@ -593,6 +593,23 @@ sptrsv_status sptrsv_mlp_grad(const float *params, const float *x, const float *
     return SPTRSV_OK;
 }
 
+sptrsv_status sptrsv_mlp_grad_noalloc(const float *params, const float *x, const float *t, int32_t m,
+                                      float *grad, float *loss, void *stream) {
+    if (m < 1) return set_err(SPTRSV_ERR_ARG, "m < 1");
+    if (m > SPTRSV_MLP_NOALLOC_MAX_SAMPLES)
+        return set_err(SPTRSV_ERR_ARG, "m above SPTRSV_MLP_NOALLOC_MAX_SAMPLES (8192): the static workspace "
+                                       "is too small; use sptrsv_mlp_grad with a workspace");
+    if (!params || !x || !t || !grad) return set_err(SPTRSV_ERR_ARG, "null argument");
+    void *ws = nullptr;
+    size_t bytes = 0;
+    int e = sptrsv_mlp_static_workspace(&ws, &bytes);
+    if (e != 0) return hip_err((hipError_t)e, "static workspace");
+    if (bytes < sptrsv_launch_mlp_workspace(m)) return set_err(SPTRSV_ERR_ARG, "static workspace too small");
+    e = sptrsv_launch_mlp_grad(params, x, t, m, grad, loss, ws, stream);
+    if (e != 0) return hip_err((hipError_t)e, "kernel launch");
+    return SPTRSV_OK;
+}
+
 sptrsv_status sptrsv_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step, float lr,
                               float beta1, float beta2, float eps, void *stream) {
     if (!params || !grad || !m1 || !m2) return set_err(SPTRSV_ERR_ARG, "null argument");

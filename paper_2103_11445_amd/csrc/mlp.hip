@@ -19,6 +19,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
+
+#include "sptrsv.h"
 
 namespace {
 
@@ -236,6 +239,49 @@ __global__ void __launch_bounds__(kBlock) mlp_adam(float *__restrict__ params, c
 int blocks_for(int64_t count) { return (int)((count + kBlock - 1) / kBlock); }
 
 }  // namespace
+
+namespace {
+
+// ---- workspace without allocation ----------------------------------------
+//
+// For callers that cannot allocate device memory: the gradient's workspace
+// for up to SPTRSV_MLP_NOALLOC_MAX_SAMPLES samples as a file-scope device
+// array.  Each GPU the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names a host-side stand-in, not the device
+// copy: the device address is looked up once per device with
+// hipGetSymbolAddress and only that address is handed to kernels.  Every
+// word of the workspace is written by the gradient's kernels before it is
+// read, so nothing needs clearing between calls; calls that overlap on one
+// GPU share the array and race.
+constexpr int32_t kStaticSamples = SPTRSV_MLP_NOALLOC_MAX_SAMPLES;
+constexpr size_t kStaticBytes =
+    sizeof(float) * ((size_t)(4 * kH + 2) * kStaticSamples +
+                     ((size_t)kStaticSamples + kChunk - 1) / kChunk * (kParams + 1));
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (guarded by g_scratch_mu)
+
+}  // namespace
+
+extern "C" int sptrsv_mlp_static_workspace(void **ptr, size_t *bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = p;
+    }
+    *ptr = g_scratch_dev[dev];
+    *bytes = kStaticBytes;
+    return 0;
+}
 
 extern "C" size_t sptrsv_launch_mlp_workspace(int32_t m) {
     const size_t nchunks = ((size_t)m + kChunk - 1) / kChunk;

@@ -216,6 +216,8 @@ extern "C" size_t sptrsv_launch_mlp_workspace(int32_t m);
 extern "C" int sptrsv_launch_mlp_forward(const float *params, const float *X, float *Y, int32_t m, void *stream);
 extern "C" int sptrsv_launch_mlp_grad(const float *params, const float *X, const float *T, int32_t m, float *grad,
                                       float *loss, void *workspace, void *stream);
+// device address (for the current device) and size of the gradient's static workspace
+extern "C" int sptrsv_mlp_static_workspace(void **ptr, size_t *bytes);
 extern "C" int sptrsv_launch_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step,
                                       float lr, float beta1, float beta2, float eps, void *stream);
 // FP32 plans: `iterations` refinement steps on x (FP64), all on stream; the

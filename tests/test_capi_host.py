@@ -615,3 +615,15 @@ def test_tiling_knob(sp):
     lib = sp.load()
     for bad in (0, 3, 32, -4):
         assert sp.STATUS[lib.sptrsv_set_tiling(plan._h, bad)] == "ERR_ARG"
+
+
+def test_mlp_grad_noalloc_argument_errors(sp):
+    """Sizes outside the static workspace and null pointers are refused
+    before any device call."""
+    lib = sp.load()
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.sptrsv_mlp_grad_noalloc(p, p, p, 0, p, p, None) == 1
+    assert lib.sptrsv_mlp_grad_noalloc(p, p, p, sp.MLP_NOALLOC_MAX_SAMPLES + 1, p, p, None) == 1
+    assert "8192" in lib.sptrsv_last_error().decode()
+    assert lib.sptrsv_mlp_grad_noalloc(None, p, p, 10, p, p, None) == 1
