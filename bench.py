@@ -68,6 +68,9 @@ TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth512", "powerlaw_4m": "pap
          "stencil2d_100": "paper"}
 TUNED_TILING = {"stencil3d_128": 8, "banded_1m": 8, "powerlaw_4m": 2, "stencil2d_100": 4}
 TUNED_WAVES = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
+# share of the waves (per mille) serving the chain queue (0 = the library's choice)
+TUNED_CHAIN = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
+CHAIN_CANDIDATES = (125, 250, 375, 500, 625, 750, 875)
 
 
 def log(*a):
@@ -85,8 +88,8 @@ def kernel_sources_hash() -> str:
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2103_11445_amd", "libsptrsv.so"), "rb") as fh:
         h.update(fh.read())
-    h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n], TUNED_WAVES[n]] for n in LARGE},
-                        sort_keys=True).encode())
+    h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n], TUNED_WAVES[n], TUNED_CHAIN[n]]
+                         for n in LARGE}, sort_keys=True).encode())
     return h.hexdigest()
 
 
@@ -305,18 +308,19 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     # ---- tuning leg
-    plans, chosen, tuning, tiling, waves = {}, {}, {}, {}, {}
+    plans, chosen, tuning, tiling, waves, chain = {}, {}, {}, {}, {}, {}
     for n in names:
         if args.no_tune or args.flush_mb:
             chosen[n] = TUNED.get(n, "paper")
             tiling[n] = TUNED_TILING.get(n, 4)
             waves[n] = TUNED_WAVES.get(n, 0)
+            chain[n] = TUNED_CHAIN.get(n, 0)
             plans[n], h = make_plan(n, chosen[n])
             if tiling[n] != 4:
                 plans[n].set_tiling(tiling[n])
                 plans[n]._buf = None
                 plans[n].upload()
-            plans[n].set_launch(waves[n])
+            plans[n].set_launch(waves[n]).set_chain_share(chain[n])
             host[n].update(h)
             continue
         best = None
@@ -378,6 +382,20 @@ def main():
             if ms < 0.97 * best_ms:
                 best_ms, waves[n] = ms, wpc
         plans[n].set_launch(waves[n])
+        # share of the waves serving the chain queue (plans with both queues)
+        chain[n] = 0
+        i = plans[n].info()
+        if 0 < i["chain_items"] < i["tiles"]:
+            for cw in CHAIN_CANDIDATES:
+                plans[n].set_chain_share(cw)
+                ms = time_solves(plans[n], n, 2)
+                tuning[n][f"{chosen[n]}/t{tiling[n]}/wpc{waves[n]}/chain{cw}"] = {
+                    "ms": ms, "levels_rw": i["levels_rw"], "entries": tuning[n][chosen[n]]["entries"],
+                    "status": plans[n].check()}
+                log(f"[tune] {n} {chosen[n]} chain share {cw}/1000: {ms:.3f} ms")
+                if ms < 0.97 * best_ms:
+                    best_ms, chain[n] = ms, cw
+        plans[n].set_chain_share(chain[n])
 
     if args.flush_mb:
         # counter runs: every solve starts with the Infinity Cache evicted
@@ -463,7 +481,8 @@ def main():
             "levels_rw": i["levels_rw"], "entries_rw": i["nnz_rw"] + i["nnz_m"],
             "flops": i["flops"], "flops_rw": i["flops_rw"], "bytes": i["bytes"],
             "bytes_rw": i["bytes_rw"], "policy": chosen[n], "terms_per_lane": tiling[n],
-            "waves_per_cu": waves[n],
+            "waves_per_cu": waves[n], "chain_share": chain[n], "launch_shape": plans[n].launch_shape(),
+            "chain_items": i["chain_items"], "items": i["tiles"],
             "rhs_mode": i["rhs_mode"], "ms_per_solve": per[n], "ms_per_solve_pct": percentiles(solve_ms[n]),
             "solves_per_s": 1000.0 / per[n],
             "plan_gbps": i["bytes_rw"] / (per[n] * 1e-3) / 1e9,
@@ -501,7 +520,8 @@ def main():
     # plans and workload; only valid for the tuned policies it was taken with
     traffic = None
     if args.workload == "large" and all(chosen[n] == TUNED[n] and tiling[n] == TUNED_TILING[n]
-                                        and waves[n] == TUNED_WAVES[n] for n in names):
+                                        and waves[n] == TUNED_WAVES[n] and chain[n] == TUNED_CHAIN[n]
+                                        for n in names):
         traffic = profiled_traffic()
     if traffic is not None:
         for n in names:

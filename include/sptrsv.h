@@ -277,6 +277,22 @@ sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_statu
  * Errors: ARG (negative, or above 8). */
 sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu);
 
+/* Share of the solve grid's waves, in per mille, that serves the chain
+ * queue (rows that some other row depends on, in level order); the others
+ * serve the sink queue (rows nothing depends on: their time is bandwidth,
+ * not the dependency chain).  0 (the default) gives each queue the share of
+ * the waves its share of the work asks for (64-lane chunks of terms plus
+ * rows packed), kept within [1/8, 7/8]; an explicit share is applied as
+ * given, leaving each queue at least one wave.  A plan with one queue
+ * ignores it.  Takes effect at the next solve.  Errors: ARG (outside
+ * [0, 1000]). */
+sptrsv_status sptrsv_set_chain_share(sptrsv_plan plan, int32_t per_mille);
+
+/* The launch shape the next solve of an uploaded plan uses: waves of the
+ * cooperative grid and, of them, waves serving the chain queue (equal to
+ * waves for a plan with one queue).  Errors: ARG, STATE (not uploaded). */
+sptrsv_status sptrsv_launch_shape(sptrsv_plan plan, int32_t *waves, int32_t *chain_waves);
+
 /* Upper bound, in ticks of the 100 MHz GPU real-time clock, on a single
  * dependency wait (default 200,000,000 = 2 s).  A wait that reaches it
  * gives up, marks the plan's status word and lets the kernel drain.
@@ -325,6 +341,10 @@ typedef struct {
     int32_t ring_segments;/* of which every term comes from the wave's LDS
                             ring; when all do, the solve runs a lighter
                             segment loop that gathers only the constants */
+    int64_t chain_items; /* work items holding rows that some other row
+                            depends on (the chain queue); the other
+                            tiles - chain_items hold only rows nothing
+                            depends on (the sink queue) */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

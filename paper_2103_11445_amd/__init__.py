@@ -22,7 +22,10 @@ __all__ = ["Plan", "Policy", "SptrsvError", "library_path", "load", "STATUS", "m
            "mlp_grad", "mlp_grad_noalloc", "mlp_adam", "probe_hop"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
+# SPTRSV_LIB points the loader at another build of the same sources (the
+# sanitizer check, tests/sanitizer_check.py, runs the host tests against an
+# AddressSanitizer / UBSan build of the host passes)
+_LIB_PATH = os.environ.get("SPTRSV_LIB") or os.path.join(_HERE, "libsptrsv.so")
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CSR", 3: "ERR_DIAG", 4: "ERR_OVERFLOW",
           5: "ERR_OOM", 6: "ERR_HIP", 7: "ERR_STATE", 8: "ERR_TIMEOUT"}
@@ -58,7 +61,8 @@ class _Info(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("seg_tiles", ctypes.c_int64),
                 ("rhs_mode", ctypes.c_int32), ("nnz_rhs", ctypes.c_int64),
                 ("rhs_segments", ctypes.c_int32), ("reg_chunks", ctypes.c_int32),
-                ("segments", ctypes.c_int32), ("ring_segments", ctypes.c_int32)]
+                ("segments", ctypes.c_int32), ("ring_segments", ctypes.c_int32),
+                ("chain_items", ctypes.c_int64)]
 
 
 _lib = None
@@ -106,6 +110,8 @@ def load():
         "sptrsv_check": (S, [P, P, P]),
         "sptrsv_set_wait_limit": (S, [P, U64]),
         "sptrsv_set_launch": (S, [P, I32]),
+        "sptrsv_set_chain_share": (S, [P, I32]),
+        "sptrsv_launch_shape": (S, [P, P, P]),
         "sptrsv_plan_info": (S, [P, P]),
         "sptrsv_plan_levels": (S, [P, I32, P]),
         "sptrsv_plan_stages": (S, [P, P, P]),
@@ -241,6 +247,18 @@ class Plan:
     def set_launch(self, waves_per_cu: int = 0):
         _check(load().sptrsv_set_launch(self._h, int(waves_per_cu)))
         return self
+
+    def set_chain_share(self, per_mille: int = 0):
+        """Share of the waves (per mille) serving the chain queue (rows other
+        rows depend on); 0 = chosen from the plan's work."""
+        _check(load().sptrsv_set_chain_share(self._h, int(per_mille)))
+        return self
+
+    def launch_shape(self):
+        """(waves, waves serving the chain queue) of the next solve."""
+        w, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().sptrsv_launch_shape(self._h, ctypes.byref(w), ctypes.byref(c)))
+        return w.value, c.value
 
     def set_wait_limit(self, ticks: int):
         _check(load().sptrsv_set_wait_limit(self._h, int(ticks)))

@@ -75,16 +75,35 @@ int launch_waves(const sptrsv::Plan &p) {
     return (int)std::max<int64_t>(1, w);
 }
 
+// Launch shape: the waves above, split between the chain queue and the sink
+// queue.  Unless set by sptrsv_set_chain_share, each queue gets the share of
+// the waves its share of the work asks for (64-lane chunks of terms and rows
+// packed), kept within [1/8, 7/8] so that neither queue is starved.
+sptrsv::LaunchShape launch_shape(const sptrsv::Plan &p) {
+    sptrsv::LaunchShape sh;
+    sh.nitems = p.ntiles;
+    sh.waves = launch_waves(p);
+    if (p.nchain <= 0 || p.nchain >= p.ntiles || sh.waves < 2) {
+        sh.nchain = p.ntiles;
+        sh.chain_waves = sh.waves;
+        return sh;
+    }
+    sh.nchain = p.nchain;
+    double share = p.chain_share > 0 ? p.chain_share / 1000.0
+                                     : (double)p.chain_work / (double)std::max<int64_t>(1, p.chain_work + p.sink_work);
+    share = std::min(7.0 / 8.0, std::max(1.0 / 8.0, share));
+    const int cw = (int)(share * sh.waves + 0.5);
+    sh.chain_waves = std::min(std::max(cw, 1), sh.waves - 1);
+    return sh;
+}
+
 // Launch shape of the stage system's solve (kRhsStage), else zeros.
-void sub_launch(const sptrsv::Plan &p, int64_t *nitems, int *waves) {
-    *nitems = 0;
-    *waves = 0;
-    if (!p.sub) return;
+sptrsv::LaunchShape sub_shape(const sptrsv::Plan &p) {
+    if (!p.sub) return sptrsv::LaunchShape{};
     sptrsv::Plan &q = *p.sub;
     q.cus = p.cus;
     q.max_waves_per_cu = p.max_waves_per_cu;
-    *nitems = q.ntiles;
-    *waves = launch_waves(q);
+    return launch_shape(q);
 }
 
 bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
@@ -247,12 +266,9 @@ extern "C" {
 sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *stream) {
     return guarded([&]() -> sptrsv_status {
         if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
-        const int waves = launch_waves(*plan);
-        int64_t sn;
-        int sw;
-        sub_launch(*plan, &sn, &sw);
+        const sptrsv::LaunchShape sh = launch_shape(*plan), sub = sub_shape(*plan);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, nullptr, 0, stream);
+                                          &sh, &sub, plan->wait_limit, b, x, nullptr, 0, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -261,12 +277,9 @@ sptrsv_status sptrsv_solve(sptrsv_plan plan, const double *b, double *x, void *s
 sptrsv_status sptrsv_solve_fp32(sptrsv_plan plan, const float *b, float *x, void *stream) {
     return guarded([&]() -> sptrsv_status {
         if (solve_args_ok(plan, b, x, 32, sizeof(float))) return SPTRSV_OK;
-        const int waves = launch_waves(*plan);
-        int64_t sn;
-        int sw;
-        sub_launch(*plan, &sn, &sw);
+        const sptrsv::LaunchShape sh = launch_shape(*plan), sub = sub_shape(*plan);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, nullptr, 0, stream);
+                                          &sh, &sub, plan->wait_limit, b, x, nullptr, 0, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -279,13 +292,9 @@ sptrsv_status sptrsv_solve_refined(sptrsv_plan plan, const double *b, double *x,
             return set_err(SPTRSV_ERR_ARG, "iterations must be in [1, 16]");
         if (!(tol >= 0.0)) return set_err(SPTRSV_ERR_ARG, "tol must be >= 0");
         if (solve_args_ok(plan, b, x, 32, sizeof(double))) return SPTRSV_OK;
-        const int waves = launch_waves(*plan);
-        int64_t sn;
-        int sw;
-        sub_launch(*plan, &sn, &sw);
+        const sptrsv::LaunchShape sh = launch_shape(*plan), sub = sub_shape(*plan);
         const int e = sptrsv_launch_refined(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                            plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, iterations, tol,
-                                            stream);
+                                            &sh, &sub, plan->wait_limit, b, x, iterations, tol, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");
         return SPTRSV_OK;
     });
@@ -377,8 +386,9 @@ sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, v
     return guarded([&]() -> sptrsv_status {
         if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
         const int32_t n = plan->n;
-        const int waves = launch_waves(*plan);
-        if (!plan->graph_exec || plan->graph_b != b || plan->graph_x != x || plan->graph_waves != waves) {
+        const sptrsv::LaunchShape sh = launch_shape(*plan), sub = sub_shape(*plan);
+        if (!plan->graph_exec || plan->graph_b != b || plan->graph_x != x || plan->graph_waves != sh.waves ||
+            plan->graph_chain_waves != sh.chain_waves) {
             drop_graph(*plan);
             hipError_t e;
             if (!plan->capture_stream) {
@@ -390,11 +400,8 @@ sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, v
             hipStream_t cs = static_cast<hipStream_t>(plan->capture_stream);
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
-            int64_t sn;
-            int sw;
-            sub_launch(*plan, &sn, &sw);
             const int le = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, n,
-                                               plan->ntiles, waves, sn, sw, plan->wait_limit, b, x, nullptr, 0, cs);
+                                               &sh, &sub, plan->wait_limit, b, x, nullptr, 0, cs);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(cs, &g);
             if (le != 0) {
@@ -409,7 +416,8 @@ sptrsv_status sptrsv_solve_graph(sptrsv_plan plan, const double *b, double *x, v
             plan->graph_exec = ge;
             plan->graph_b = b;
             plan->graph_x = x;
-            plan->graph_waves = waves;
+            plan->graph_waves = sh.waves;
+            plan->graph_chain_waves = sh.chain_waves;
         }
         hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(plan->graph_exec), static_cast<hipStream_t>(stream));
         if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
@@ -442,6 +450,22 @@ sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu) {
     if (waves_per_cu > sptrsv::kMaxWavesPerCU)
         return set_err(SPTRSV_ERR_ARG, "waves_per_cu above 8: co-residency of the grid is not proven there");
     plan->waves_per_cu = waves_per_cu;
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_set_chain_share(sptrsv_plan plan, int32_t per_mille) {
+    if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+    if (per_mille < 0 || per_mille > 1000) return set_err(SPTRSV_ERR_ARG, "per_mille must be in [0, 1000]");
+    plan->chain_share = per_mille;
+    return SPTRSV_OK;
+}
+
+sptrsv_status sptrsv_launch_shape(sptrsv_plan plan, int32_t *waves, int32_t *chain_waves) {
+    if (!plan || !waves || !chain_waves) return set_err(SPTRSV_ERR_ARG, "null argument");
+    if (!plan->uploaded) return set_err(SPTRSV_ERR_STATE, "plan not uploaded");
+    const sptrsv::LaunchShape sh = launch_shape(*plan);
+    *waves = sh.waves;
+    *chain_waves = sh.chain_waves;
     return SPTRSV_OK;
 }
 
@@ -481,6 +505,7 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->reg_chunks = p.layout.reg_chunks;
     o->segments = p.nseg;
     o->ring_segments = p.ring_segs;
+    o->chain_items = p.nchain;
     return SPTRSV_OK;
 }
 
@@ -526,12 +551,9 @@ sptrsv_status sptrsv_solve_stamped(sptrsv_plan plan, const double *b, double *x,
     return guarded([&]() -> sptrsv_status {
         if (solve_args_ok(plan, b, x, 64, sizeof(double))) return SPTRSV_OK;
         if (!stamps) return set_err(SPTRSV_ERR_ARG, "stamps is NULL");
-        const int waves = launch_waves(*plan);
-        int64_t sn;
-        int sw;
-        sub_launch(*plan, &sn, &sw);
+        const sptrsv::LaunchShape sh = launch_shape(*plan), sub = sub_shape(*plan);
         const int e = sptrsv_launch_solve(static_cast<const unsigned char *>(plan->dev), &plan->layout, plan->n,
-                                          plan->ntiles, waves, sn, sw, plan->wait_limit, b, x,
+                                          &sh, &sub, plan->wait_limit, b, x,
                                           reinterpret_cast<unsigned long long *>(stamps),
                                           plan->ntiles + plan->nseg_tiles, stream);
         if (e != 0) return hip_err((hipError_t)e, "kernel launch");

@@ -17,6 +17,11 @@
 // of one level; its terms occupy `nchunks` chunks of 64 slots, the t-th term
 // of the tile's r-th row at chunk t / g, lane r * g + t % g.  A term is an
 // x-term (column k, coefficient -L'_ik); unused slots hold INT32_MIN.
+// Columns are slots, not rows: the solve keeps x in slot (schedule) order
+// in the image, where a level's rows sit side by side, so a tile's results
+// go to a few consecutive lines and the values a level gathers from the one
+// before it are near each other; every value is also stored once, in the
+// caller's order, into the caller's x.
 //
 // Segments.  A level is narrow when its rows fit in at most kNarrowTiles
 // tiles of kSegChunks chunks (g = 64 / rows-per-tile, as many lanes per row
@@ -28,11 +33,15 @@
 // and gathers nothing but the constants; its pads point at the ring's zero
 // slot (column n + kRing).
 // Segment tiles are stored with a fixed stride, lane-major (each lane's
-// kSegChunks columns, then its coefficients, contiguous; one row id / meta
-// pair and one diagonal per lane) so the wave prefetches a tile with a few
+// kSegChunks columns, then its coefficients, contiguous; one {row id, meta,
+// slot} record and one diagonal per lane) so the wave prefetches a tile with a few
 // wide loads, several tiles ahead, without reading a descriptor first.
 //
 // Items are ordered by level, so an item only depends on items before it.
+// Within a wide level, rows that some other row depends on (the chain) and
+// rows nothing depends on (sinks) go to separate tiles: chain tiles and
+// segments form the first queue of items, sink tiles the second (each in
+// level order), served by separate waves.  A sink never delays a chain row.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -159,13 +168,19 @@ void pack(Plan &p) {
     struct Item { int kind; int64_t a, b; int32_t level; };  // wide: a = wide tile; seg: a = first seg tile, b = count
     std::vector<Tile> tiles;
     std::vector<SegTile> stiles;
-    std::vector<Item> items;
+    std::vector<Item> items, sink_items;  // the chain queue, the sink queue
+    // rows of L' that another row of L' depends on
+    std::vector<char> needed((size_t)n, 0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q)
+            needed[(size_t)p.lp_col[(size_t)q]] = 1;
     std::vector<int32_t> seg_of_slot((size_t)n, -1);   // segment id of each slot
     int64_t nchunks = 0;
     int32_t slot = 0, nseg = 0;
 
-    // rows[0, count) of level l (ascending) as wide tiles, binned by length
-    auto wide_level = [&](const int32_t *rows, int32_t count, int32_t l) {
+    // rows[0, count) of level l (ascending) as wide tiles, binned by length,
+    // appended to the chain queue or, for sinks, to the sink queue
+    auto wide_tiles = [&](const int32_t *rows, int32_t count, int32_t l, bool sink) {
         int32_t cnt[kBins] = {0};
         for (int32_t q = 0; q < count; ++q) ++cnt[bin_of(len[(size_t)rows[q]], p.terms_per_lane)];
         int32_t start[kBins];
@@ -187,12 +202,20 @@ void pack(Plan &p) {
                 int64_t mx = 0;
                 for (int32_t r = 0; r < nr; ++r) mx = std::max(mx, len[(size_t)slot_row[(size_t)(s + r)]]);
                 const int64_t nch = (mx + (1 << g) - 1) >> g;
-                items.push_back({0, (int64_t)tiles.size(), 0, l});
+                (sink ? sink_items : items).push_back({0, (int64_t)tiles.size(), 0, l});
                 tiles.push_back({nchunks, s, (int32_t)nch, nr, g});
                 nchunks += nch;
             }
         }
         slot = acc;
+    };
+    std::vector<int32_t> chain_rows, sink_rows;
+    auto wide_level = [&](const int32_t *rows, int32_t count, int32_t l) {
+        chain_rows.clear();
+        sink_rows.clear();
+        for (int32_t q = 0; q < count; ++q) (needed[(size_t)rows[q]] ? chain_rows : sink_rows).push_back(rows[q]);
+        if (!chain_rows.empty()) wide_tiles(chain_rows.data(), (int32_t)chain_rows.size(), l, false);
+        if (!sink_rows.empty()) wide_tiles(sink_rows.data(), (int32_t)sink_rows.size(), l, true);
     };
     // a new segment
     auto open_segment = [&]() {
@@ -306,6 +329,18 @@ void pack(Plan &p) {
             if (l + 1 == L || !in_seg[(size_t)l + 1]) close_segment();
         }
     }
+    const int64_t nchain = (int64_t)items.size();
+    // work of each queue: 64-lane chunks of terms plus one per tile for the
+    // rows (segment tiles: kSegChunks chunks each)
+    auto work = [&](const std::vector<Item> &v) {
+        int64_t w = 0;
+        for (const Item &I : v) w += I.kind == 1 ? I.b * (kSegChunks + 1) : tiles[(size_t)I.a].nch + 1;
+        return w;
+    };
+    p.chain_work = work(items);
+    p.sink_work = work(sink_items);
+    items.insert(items.end(), sink_items.begin(), sink_items.end());
+    sink_items.clear();
     if (nchunks > INT32_MAX || (int64_t)items.size() > INT32_MAX || (int64_t)stiles.size() * 64 > INT32_MAX)
         throw Error{SPTRSV_ERR_OVERFLOW, "device image needs more than INT32_MAX chunks"};
     std::vector<int32_t> slot_of_row((size_t)n);
@@ -386,7 +421,7 @@ void pack(Plan &p) {
     Ly.sval = off;
     off = align256(off + (size_t)nst * kSegChunks * 64 * vb);
     Ly.srow = off;
-    off = align256(off + (size_t)nst * 64 * 8);
+    off = align256(off + (size_t)nst * 64 * 16);
     Ly.sdiag = off;
     off = align256(off + (size_t)nst * 64 * vb);
     Ly.mtiles = off;
@@ -398,6 +433,8 @@ void pack(Plan &p) {
     Ly.mval = off;
     off = align256(off + (size_t)mchunks * 64 * vb);
     Ly.bp = off;
+    off = align256(off + (size_t)n * vb);
+    Ly.xs = off;
     off = align256(off + (size_t)n * vb);
     Ly.nmtiles = (int64_t)mtiles.size();
     Ly.rhs_mode = rhs_mode;
@@ -438,7 +475,7 @@ void pack(Plan &p) {
     int32_t *tcol = reinterpret_cast<int32_t *>(img + Ly.tcol);
     int32_t *desc = reinterpret_cast<int32_t *>(img + Ly.tiles);
     int32_t *scol = reinterpret_cast<int32_t *>(img + Ly.scol);
-    int32_t *srow = reinterpret_cast<int32_t *>(img + Ly.srow);  // {row, meta} per lane
+    int32_t *srow = reinterpret_cast<int32_t *>(img + Ly.srow);  // {row, meta, slot, 0} per lane
     // value sections: FP64, or rounded to nearest FP32
     auto putv = [&](size_t section, int64_t idx, double v) {
         if (f32)
@@ -448,7 +485,7 @@ void pack(Plan &p) {
     };
     std::fill(tcol, tcol + nchunks * 64, kPad);
     std::fill(scol, scol + nst * kSegChunks * 64, kPad);
-    for (int64_t q = 0; q < nst * 64; ++q) srow[2 * q] = -1;
+    for (int64_t q = 0; q < nst * 64; ++q) srow[4 * q] = -1;
     // the device image speaks the caller's indices (reversed for upper
     // input; a batched union is numbered like the callers' blocks already)
     auto orig = [&](int32_t i) { return p.upper ? n - 1 - i : i; };
@@ -462,12 +499,10 @@ void pack(Plan &p) {
     auto row_terms = [&](int32_t i, int32_t seg, int32_t first_slot_of_tile, auto &&put) {
         for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q) {
             const int32_t k = p.lp_col[(size_t)q];
-            int32_t col = orig(k);
-            if (seg >= 0) {
-                const int32_t sk = slot_of_row[(size_t)k];
-                if (seg_of_slot[(size_t)sk] == seg && first_slot_of_tile - sk <= kRing)
-                    col = n + ((sk - seg_first[(size_t)seg]) & (kRing - 1));
-            }
+            const int32_t sk = slot_of_row[(size_t)k];
+            int32_t col = sk;  // x is gathered in slot order
+            if (seg >= 0 && seg_of_slot[(size_t)sk] == seg && first_slot_of_tile - sk <= kRing)
+                col = n + ((sk - seg_first[(size_t)seg]) & (kRing - 1));
             put(col, -p.lp_val[(size_t)q]);
         }
     };
@@ -486,13 +521,14 @@ void pack(Plan &p) {
             for (int64_t st = I.a; st < I.a + I.b; ++st) {
                 const SegTile &T = stiles[(size_t)st];
                 const int32_t g = 1 << T.lg;
-                for (int32_t lane = 0; lane < 64; ++lane) srow[2 * (st * 64 + lane) + 1] = T.lg;
+                for (int32_t lane = 0; lane < 64; ++lane) srow[4 * (st * 64 + lane) + 1] = T.lg;
                 for (int32_t r = 0; r < T.nrows; ++r) {
                     const int32_t s = T.row_off + r;
                     const int32_t i = slot_row[(size_t)s];
                     const int64_t lead = st * 64 + r * g;
-                    srow[2 * lead] = orig(i);
-                    srow[2 * lead + 1] = T.lg | (((s - seg_first[(size_t)sid]) & (kRing - 1)) << 8);
+                    srow[4 * lead] = orig(i);
+                    srow[4 * lead + 1] = T.lg | (((s - seg_first[(size_t)sid]) & (kRing - 1)) << 8);
+                    srow[4 * lead + 2] = s;
                     putv(Ly.sdiag, lead, p.lp_val[(size_t)p.lp_ptr[(size_t)i + 1] - 1]);
                     int64_t t_ = 0;
                     row_terms(i, sid, T.row_off, [&](int32_t col, double v) {
@@ -593,6 +629,7 @@ void pack(Plan &p) {
     for (size_t it = 0; it < items.size(); ++it) p.stamp_level[it] = items[it].level;
     for (size_t st = 0; st < stiles.size(); ++st) p.stamp_level[items.size() + st] = stiles[st].level;
     p.ntiles = (int64_t)items.size();
+    p.nchain = nchain;
     p.nchunks = nchunks;
     p.nseg = nseg;
     p.nseg_tiles = nst;

@@ -50,6 +50,16 @@ enum RhsMode : int32_t {
 
 struct Layout;
 
+// Launch of one cooperative solve: work items, how many of them form the
+// chain queue (the rest are sinks), waves, and how many waves serve the
+// chain queue.  One queue: nchain = nitems and chain_waves = waves.
+struct LaunchShape {
+    int64_t nitems = 0;
+    int64_t nchain = 0;
+    int waves = 0;
+    int chain_waves = 0;
+};
+
 // Device image layout: byte offsets of each section inside the caller's
 // buffer.  Sections are 256-byte aligned.  Values (diag, tval, sval, sdiag)
 // are FP64, or FP32 in a plan stored in FP32 (value_bytes 4).
@@ -65,13 +75,13 @@ struct Layout {
                            //   or segment {first segment tile, count, 0, 1<<31}
     size_t rows = 0;       // int32[n]      row id of each packed slot
     size_t diag = 0;       // double[n]     diagonal of each packed slot
-    size_t tcol = 0;       // int32[64*nchunks] term column (0..n-1 x-term, ~j b-term, INT32_MIN pad)
+    size_t tcol = 0;       // int32[64*nchunks] term column: slot of the x-term's row, INT32_MIN pad
     size_t tval = 0;       // double[64*nchunks] term coefficient (x-terms negated)
     size_t scol = 0;       // int32[nseg_tiles][64][kSegChunks] as tcol, plus n + ring index for LDS x-terms
                            // (n + kRing, a zero slot, for the pads of a segment without gathers)
     size_t sval = 0;       // double[nseg_tiles][64][kSegChunks]
-    size_t srow = 0;       // int32[nseg_tiles][64][2]: row finished by the lane (-1 if none),
-                           //   log2 lanes per row | ring index << 8
+    size_t srow = 0;       // int32[nseg_tiles][64][4]: row finished by the lane (-1 if none),
+                           //   log2 lanes per row | ring index << 8, its slot, 0
     size_t sdiag = 0;      // double[nseg_tiles][64] its diagonal
     // right-hand side b' = b + M b, computed by a parallel pass before the solve
     size_t mtiles = 0;     // int4[nmtiles]: {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
@@ -79,6 +89,7 @@ struct Layout {
     size_t mcol = 0;       // int32[64*mchunks] device index of b_j (INT32_MIN pad)
     size_t mval = 0;       // double[64*mchunks] M_ij
     size_t bp = 0;         // double[n] b' (kRhsMPass) or y (kRhsStage), device indices
+    size_t xs = 0;         // double[n] x in slot order: the solve's readiness flags and gathered values
     int64_t nmtiles = 0;
     int64_t nnz_rhs = 0;   // entries the right-hand-side step reads (M, or L_B)
     // FP32 plans only: what iterative refinement needs next to the FP32
@@ -157,6 +168,8 @@ struct Plan {
     Layout layout;
     std::vector<unsigned char> image;
     int64_t ntiles = 0;      // work items (wide tiles and segments)
+    int64_t nchain = 0;      // of which the chain queue (the rest hold only rows nothing depends on)
+    int64_t chain_work = 0, sink_work = 0;  // 64-lane chunks plus rows packed in each queue
     int64_t nchunks = 0;
     int32_t nseg = 0;        // segments
     int64_t nseg_tiles = 0;  // tiles inside segments
@@ -173,13 +186,14 @@ struct Plan {
     int cus = 0;                         // compute units of the device uploaded to
     int max_waves_per_cu = 0;            // co-resident solve workgroups per CU
     int waves_per_cu = 0;                // requested; 0 = chosen from the plan's shape
+    int chain_share = 0;                 // chain queue's share of the waves requested (per mille); 0 = chosen
     uint64_t wait_limit = 200000000ull;  // 2 s at 100 MHz
 
     // ---- captured solve graph (sptrsv_solve_graph)
     void *graph_exec = nullptr;          // hipGraphExec_t
     void *capture_stream = nullptr;      // hipStream_t owned by the plan
     const void *graph_b = nullptr, *graph_x = nullptr;
-    int graph_waves = 0;
+    int graph_waves = 0, graph_chain_waves = 0;
     ~Plan();
 };
 
@@ -207,8 +221,8 @@ void pack(Plan &p);
 // real-time clock (100 MHz) as every item and every segment tile completes
 // (slots [0, nitems) and nitems + segment tile), and its start at start_slot.
 // sub_nitems / sub_waves: the stage system's solve (kRhsStage).
-extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay,
-                                   int32_t n, int64_t nitems, int waves, int64_t sub_nitems, int sub_waves,
+extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
+                                   const sptrsv::LaunchShape *sh, const sptrsv::LaunchShape *sub,
                                    uint64_t wait_limit, const void *b, void *x, unsigned long long *stamps,
                                    int64_t start_slot, void *stream);
 // mlp.hip -- cost model kernels (FP32 parameter vector of 4673 floats)
@@ -222,8 +236,8 @@ extern "C" int sptrsv_launch_mlp_adam(float *params, const float *grad, float *m
                                       float lr, float beta1, float beta2, float eps, void *stream);
 // FP32 plans: `iterations` refinement steps on x (FP64), all on stream; the
 // steps after convergence (correction <= tol) skip their work on the device.
-extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay,
-                                     int32_t n, int64_t nitems, int waves, int64_t sub_nitems, int sub_waves,
+extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
+                                     const sptrsv::LaunchShape *sh, const sptrsv::LaunchShape *sub,
                                      uint64_t wait_limit, const double *b, double *x, int iterations,
                                      double tol, void *stream);
 extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu);

@@ -8,6 +8,11 @@
 //     level of L'; wave w takes items w, w+W, w+2W, ...  An item only depends
 //     on rows of earlier items, and the wave holding the lowest unfinished
 //     item has finished all its earlier items, so the grid always drains.
+//   * Rows that no other row depends on (sinks) are off the dependency
+//     chain: they are packed into a second queue, in level order, served by
+//     waves of their own, so the chain's waves only carry rows something
+//     waits for.  Chain rows depend only on chain rows (nothing depends on a
+//     sink), so the argument above holds for each queue.
 //   * Per-row readiness instead of a barrier per level: x itself is the flag.
 //     Before the solve every x_i is set to a signalling-NaN bit pattern that
 //     no arithmetic result can carry (results are quiet NaNs at worst).  A
@@ -97,7 +102,7 @@ struct SolveArgs {
     const T *tval;
     const int32_t *scol;
     const T *sval;
-    const int2 *srow;
+    const int4 *srow;
     const T *sdiag;
     sptrsv::Workspace *ws;
     const unsigned *skip;  // refinement: the grid returns at once if *skip (NULL: never)
@@ -105,9 +110,17 @@ struct SolveArgs {
     long long start_slot;        // stamps[start_slot]: the clock when the grid started
     const T *b;  // b' = b + M b (written by prepare), y (b' = diag * y), or b
     int bscale;  // the constants are y: b'_i = diag_i * y_i
-    T *x;
+    T *x;        // x in slot (schedule) order, its own readiness flag; terms index it
+    T *xout;     // the caller's x, in its own order: every row stored once, plainly
     long long nitems;
     long long waves;
+    // two work queues: items [0, nchain) hold the rows some row of a later
+    // item depends on (the chain), in level order, taken round-robin by
+    // waves [0, wchain); items [nchain, nitems) hold rows nothing depends
+    // on (sinks), in level order, taken by the other waves.  One queue:
+    // nchain = nitems, wchain = waves.
+    long long nchain;
+    long long wchain;
     unsigned long long wait_limit;
     int32_t n;
 };
@@ -277,7 +290,7 @@ __device__ inline int4 unpack_item(int w) {
                      __builtin_amdgcn_readlane(w, 2), __builtin_amdgcn_readlane(w, 3));
 }
 
-// x (and y of the stage system) := not ready.
+// The slot-ordered x of the solve (and of the stage system's solve) := not ready.
 template <typename T>
 __global__ void fill_not_ready(typename Val<T>::Bits *__restrict__ x, typename Val<T>::Bits *__restrict__ y,
                                int32_t n, const unsigned *skip) {
@@ -298,17 +311,20 @@ struct PrepArgs {
     const T *val;            // M_ij
     const T *b;
     T *bp;                   // out: b'
-    typename Val<T>::Bits *x;  // out: the not-ready pattern
+    typename Val<T>::Bits *x;  // out: the not-ready pattern, over the slot-ordered x
+    int32_t n;
     long long ntiles;
     const unsigned *skip;    // refinement: return at once if *skip
 };
 
-// b'_i = b_i + sum_j M_ij b_j and x_i = not ready, for every row: one wave per
-// M tile (grid-stride), its chunks in groups of four with every load issued
-// before the first use.  Nothing here waits on another wave.
+// b'_i = b_i + sum_j M_ij b_j for every row (one wave per M tile,
+// grid-stride, its chunks in groups of four with every load issued before
+// the first use) and x := not ready.  Nothing here waits on another wave.
 template <typename T>
 __global__ void __launch_bounds__(256) prepare(PrepArgs<T> a) {
     if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x)
+        a.x[i] = Val<T>::kNotReady;
     const int lane = threadIdx.x & 63;
     const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
     for (long long t = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < a.ntiles; t += nw) {
@@ -340,7 +356,6 @@ __global__ void __launch_bounds__(256) prepare(PrepArgs<T> a) {
         if (active && (lane & ((1 << lg) - 1)) == 0) {
             const int32_t row = a.rows[d.y + (lane >> lg)];
             a.bp[row] = a.b[row] + acc;
-            a.x[row] = Val<T>::kNotReady;
         }
     }
 }
@@ -400,7 +415,7 @@ template <typename T>
 struct SegSlot {
     int4 col;                                  // term columns
     Four<T> v;                                 // term coefficients
-    int2 rm;                                   // {row (-1 if the lane finishes none), meta}
+    int4 rm;                                   // {row (-1 if the lane finishes none), meta, slot, 0}
     T diag;
     typename Val<T>::Bits g[kSegChunks];       // gathered b / external x (bits)
     T bi;                                      // b of the lane's row (meaningful where rm.x >= 0)
@@ -431,7 +446,7 @@ __device__ inline void seg_load(const SolveArgs<T> &a, long long st, int lane, S
     const size_t ln = (size_t)st * 64 + lane;
     S.col = reinterpret_cast<const int4 *>(a.scol)[ln];
     load_four(a.sval, ln, S.v);
-    S.rm = a.srow[ln];
+    S.rm = a.srow[ln];  // one 16-byte load
     S.diag = a.sdiag[ln];
 }
 
@@ -480,8 +495,9 @@ __device__ inline void seg_finish(const SolveArgs<T> &a, SegSlot<T> &S, T *ring)
         const T bi = a.bscale ? S.bi * S.diag : S.bi;
         const T xi = (bi + acc) / S.diag;
         ring[S.rm.y >> 8] = xi;
-        __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + S.rm.x, Val<T>::bits(xi),
+        __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + S.rm.z, Val<T>::bits(xi),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.xout[S.rm.x] = xi;
     }
 }
 
@@ -532,21 +548,25 @@ template <typename T, bool kStamp, int kReg, bool kRingSegs>
 __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     __shared__ T ring[kRing + 1];  // x of the segment's last kRing rows, then a zero slot
     const int lane = threadIdx.x;
-    long long i = blockIdx.x;
     if (lane == 0) ring[kRing] = T(0);
-    if (kStamp && i == 0 && lane == 0) a.stamps[a.start_slot] = __builtin_amdgcn_s_memrealtime();
-    if (i >= a.nitems) return;
+    if (kStamp && blockIdx.x == 0 && lane == 0) a.stamps[a.start_slot] = __builtin_amdgcn_s_memrealtime();
+    // this wave's queue: its first item, stride and end
+    const bool on_chain = (long long)blockIdx.x < a.wchain;
+    const long long stride = on_chain ? a.wchain : a.waves - a.wchain;
+    const long long end = on_chain ? a.nchain : a.nitems;
+    long long i = on_chain ? (long long)blockIdx.x : a.nchain + ((long long)blockIdx.x - a.wchain);
+    if (i >= end) return;
     if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     int4 d = unpack_item(load_item(a, i, lane));
     Tile<T, kReg> cur;
     if (!is_segment(d)) load_tile(a, d, lane, cur);
-    int wnext = load_item(a, i + a.waves, lane);  // raw descriptor of the next item
+    int wnext = load_item(a, i + stride, lane);  // raw descriptor of the next item
     for (;;) {
-        const long long in = i + a.waves, inn = in + a.waves;
+        const long long in = i + stride, inn = in + stride;
         if (is_segment(d)) {
             run_segment<T, kStamp, kRingSegs>(a, d, lane, ring);
             if (kStamp && lane == 0) a.stamps[i] = __builtin_amdgcn_s_memrealtime();
-            if (in >= a.nitems) break;
+            if (in >= end) break;
             d = unpack_item(wnext);
             if (!is_segment(d)) load_tile(a, d, lane, cur);
             wnext = load_item(a, inn, lane);
@@ -568,7 +588,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         __builtin_amdgcn_sched_barrier(0);
         // 2. the next tile's terms and the descriptor after it
         Tile<T, kReg> nxt;
-        const bool nwide = in < a.nitems && !is_segment(dnext);
+        const bool nwide = in < end && !is_segment(dnext);
         load_tile(a, nwide ? dnext : d, lane, nxt);
         const int wnn = load_item(a, inn, lane);
         asm volatile("" ::: "memory");
@@ -608,11 +628,12 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         if (lead) {
             const T bi = a.bscale ? braw * cur.diag : braw;
             const T xi = (bi + acc) / cur.diag;
-            __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + cur.row, Val<T>::bits(xi),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + cur.d.y + (lane >> (cur.d.w & 0xff)),
+                               Val<T>::bits(xi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.xout[cur.row] = xi;
         }
         if (kStamp && lane == 0) a.stamps[i] = __builtin_amdgcn_s_memrealtime();
-        if (in >= a.nitems) break;
+        if (in >= end) break;
         cur = nxt;
         d = dnext;
         wnext = wnn;
@@ -757,9 +778,9 @@ __global__ void __launch_bounds__(kRefBlock) refine_residual(const int4 *__restr
 }
 
 template <typename T>
-SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n, int64_t nitems,
-                        int waves, uint64_t wait_limit, const void *b, void *x, const unsigned *skip,
-                        unsigned long long *stamps = nullptr, int64_t start_slot = 0) {
+SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
+                        const sptrsv::LaunchShape &sh, uint64_t wait_limit, const void *b, void *x,
+                        const unsigned *skip, unsigned long long *stamps = nullptr, int64_t start_slot = 0) {
     SolveArgs<T> a;
     a.stamps = stamps;
     a.start_slot = start_slot;
@@ -770,15 +791,18 @@ SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int
     a.tval = reinterpret_cast<const T *>(dev + lay->tval);
     a.scol = reinterpret_cast<const int32_t *>(dev + lay->scol);
     a.sval = reinterpret_cast<const T *>(dev + lay->sval);
-    a.srow = reinterpret_cast<const int2 *>(dev + lay->srow);
+    a.srow = reinterpret_cast<const int4 *>(dev + lay->srow);
     a.sdiag = reinterpret_cast<const T *>(dev + lay->sdiag);
     a.ws = reinterpret_cast<sptrsv::Workspace *>(const_cast<unsigned char *>(dev) + lay->workspace);
     a.skip = skip;
     a.b = static_cast<const T *>(b);
     a.bscale = 0;
-    a.x = static_cast<T *>(x);
-    a.nitems = nitems;
-    a.waves = waves;
+    a.x = reinterpret_cast<T *>(const_cast<unsigned char *>(dev) + lay->xs);
+    a.xout = static_cast<T *>(x);
+    a.nitems = sh.nitems;
+    a.waves = sh.waves;
+    a.nchain = sh.nchain;
+    a.wchain = sh.chain_waves;
     a.wait_limit = wait_limit;
     a.n = n;
     return a;
@@ -802,7 +826,7 @@ hipError_t launch_tiles(SolveArgs<T> a, int waves, const sptrsv::Layout *lay, hi
 }
 
 template <typename T>
-hipError_t launch_prepare(const unsigned char *dev, const sptrsv::Layout *lay, const void *b, void *x,
+hipError_t launch_prepare(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n, const void *b,
                           const unsigned *skip, hipStream_t s) {
     PrepArgs<T> p;
     p.tiles = reinterpret_cast<const int4 *>(dev + lay->mtiles);
@@ -811,7 +835,8 @@ hipError_t launch_prepare(const unsigned char *dev, const sptrsv::Layout *lay, c
     p.val = reinterpret_cast<const T *>(dev + lay->mval);
     p.b = static_cast<const T *>(b);
     p.bp = reinterpret_cast<T *>(const_cast<unsigned char *>(dev) + lay->bp);
-    p.x = static_cast<typename Val<T>::Bits *>(x);
+    p.x = reinterpret_cast<typename Val<T>::Bits *>(const_cast<unsigned char *>(dev) + lay->xs);
+    p.n = n;
     p.ntiles = lay->nmtiles;
     p.skip = skip;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (lay->nmtiles + 3) / 4));
@@ -823,11 +848,13 @@ int fill_blocks(int32_t n) { return (int)std::min<int64_t>(2048, ((int64_t)n + 2
 
 // One solve of L x = b in the plan's value type: the right-hand-side step of
 // the plan's mode, then the dependent solve.  With kRhsStage the stage
-// system runs first (into y = the image's bp vector) and shares the main
-// workspace, so a failed wait in either is reported by the same status word.
+// system runs first (its output y, in the caller's order, is the image's bp
+// vector) and shares the main workspace, so a failed wait in either is
+// reported by the same status word.  The readiness arrays (x in slot order,
+// the main image's and the stage system's) are set to not-ready first.
 template <typename T, bool kStamp>
-hipError_t solve_once(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n, int64_t nitems, int waves,
-                      int64_t sub_nitems, int sub_waves, uint64_t wait_limit, const void *b, void *x,
+hipError_t solve_once(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n, const sptrsv::LaunchShape &sh,
+                      const sptrsv::LaunchShape &sub, uint64_t wait_limit, const void *b, void *x,
                       const unsigned *skip, unsigned long long *stamps, int64_t start_slot, hipStream_t s) {
     using B = typename Val<T>::Bits;
     unsigned char *d = const_cast<unsigned char *>(dev);
@@ -835,25 +862,26 @@ hipError_t solve_once(const unsigned char *dev, const sptrsv::Layout *lay, int32
     const void *rhs = b;
     int bscale = 0;
     if (lay->rhs_mode == sptrsv::kRhsMPass) {
-        if ((e = launch_prepare<T>(dev, lay, b, x, skip, s)) != hipSuccess) return e;
+        if ((e = launch_prepare<T>(dev, lay, n, b, skip, s)) != hipSuccess) return e;
         rhs = d + lay->bp;
     } else {
-        B *y = lay->rhs_mode == sptrsv::kRhsStage ? reinterpret_cast<B *>(d + lay->bp) : nullptr;
-        hipLaunchKernelGGL(fill_not_ready<T>, dim3(fill_blocks(n)), dim3(256), 0, s, static_cast<B *>(x), y, n,
-                           skip);
+        const bool stage = lay->rhs_mode == sptrsv::kRhsStage;
+        B *xs = reinterpret_cast<B *>(d + lay->xs);
+        B *sub_xs = stage ? reinterpret_cast<B *>(d + lay->sub + lay->sub_layout->xs) : nullptr;
+        hipLaunchKernelGGL(fill_not_ready<T>, dim3(fill_blocks(n)), dim3(256), 0, s, xs, sub_xs, n, skip);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (y) {
-            SolveArgs<T> sa = solve_args<T>(dev + lay->sub, lay->sub_layout, n, sub_nitems, sub_waves, wait_limit,
-                                            b, y, skip);
+        if (stage) {
+            T *y = reinterpret_cast<T *>(d + lay->bp);
+            SolveArgs<T> sa = solve_args<T>(dev + lay->sub, lay->sub_layout, n, sub, wait_limit, b, y, skip);
             sa.ws = reinterpret_cast<sptrsv::Workspace *>(d + lay->workspace);
-            if ((e = launch_tiles<T, false>(sa, sub_waves, lay->sub_layout, s)) != hipSuccess) return e;
+            if ((e = launch_tiles<T, false>(sa, sub.waves, lay->sub_layout, s)) != hipSuccess) return e;
             rhs = y;
             bscale = 1;
         }
     }
-    SolveArgs<T> a = solve_args<T>(dev, lay, n, nitems, waves, wait_limit, rhs, x, skip, stamps, start_slot);
+    SolveArgs<T> a = solve_args<T>(dev, lay, n, sh, wait_limit, rhs, x, skip, stamps, start_slot);
     a.bscale = bscale;
-    return launch_tiles<T, kStamp>(a, waves, lay, s);
+    return launch_tiles<T, kStamp>(a, sh.waves, lay, s);
 }
 
 // ------------------------------------------------------------ hop probe --
@@ -941,24 +969,21 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
 }
 
 extern "C" int sptrsv_launch_solve(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
-                                   int64_t nitems, int waves, int64_t sub_nitems, int sub_waves, uint64_t wait_limit,
-                                   const void *b, void *x, unsigned long long *stamps, int64_t start_slot,
-                                   void *stream) {
+                                   const sptrsv::LaunchShape *sh, const sptrsv::LaunchShape *sub,
+                                   uint64_t wait_limit, const void *b, void *x, unsigned long long *stamps,
+                                   int64_t start_slot, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (lay->value_bytes == 4) {
         if (stamps) return (int)hipErrorNotSupported;
-        return (int)solve_once<float, false>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, b, x,
-                                             nullptr, nullptr, 0, s);
+        return (int)solve_once<float, false>(dev, lay, n, *sh, *sub, wait_limit, b, x, nullptr, nullptr, 0, s);
     }
     if (stamps)
-        return (int)solve_once<double, true>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, b, x,
-                                             nullptr, stamps, start_slot, s);
-    return (int)solve_once<double, false>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, b, x,
-                                          nullptr, nullptr, 0, s);
+        return (int)solve_once<double, true>(dev, lay, n, *sh, *sub, wait_limit, b, x, nullptr, stamps, start_slot, s);
+    return (int)solve_once<double, false>(dev, lay, n, *sh, *sub, wait_limit, b, x, nullptr, nullptr, 0, s);
 }
 
 extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Layout *lay, int32_t n,
-                                     int64_t nitems, int waves, int64_t sub_nitems, int sub_waves,
+                                     const sptrsv::LaunchShape *sh, const sptrsv::LaunchShape *sub,
                                      uint64_t wait_limit, const double *b, double *x, int iterations, double tol,
                                      void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -972,8 +997,8 @@ extern "C" int sptrsv_launch_refined(const unsigned char *dev, const sptrsv::Lay
     if (e != hipSuccess) return (int)e;
     // each step: the FP32 solve of L d = r32 (right-hand-side step included)
     for (int t = 0; t < iterations; ++t) {
-        if ((e = solve_once<float, false>(dev, lay, n, nitems, waves, sub_nitems, sub_waves, wait_limit, r32, d32,
-                                          &ws->done, nullptr, 0, s)) != hipSuccess)
+        if ((e = solve_once<float, false>(dev, lay, n, *sh, *sub, wait_limit, r32, d32, &ws->done, nullptr, 0,
+                                          s)) != hipSuccess)
             return (int)e;
         hipLaunchKernelGGL(refine_update, dim3(grid), dim3(kRefBlock), 0, s, x, d32, ws, n, t);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;

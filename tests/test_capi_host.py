@@ -617,6 +617,18 @@ def test_tiling_knob(sp):
         assert sp.STATUS[lib.sptrsv_set_tiling(plan._h, bad)] == "ERR_ARG"
 
 
+def test_hop_probe_argument_errors(sp):
+    """Argument checks of the hop probe happen before any device call."""
+    lib = sp.load()
+    ns = ctypes.c_double()
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.sptrsv_probe_hop(100, 0, None, 64, ctypes.byref(ns), None) == 1
+    assert lib.sptrsv_probe_hop(1, 0, p, 64, ctypes.byref(ns), None) == 1
+    assert lib.sptrsv_probe_hop(100, 0, p, 16, ctypes.byref(ns), None) == 1
+    assert lib.sptrsv_probe_hop(100, 0, p, 64, None, None) == 1
+
+
 def test_mlp_grad_noalloc_argument_errors(sp):
     """Sizes outside the static workspace and null pointers are refused
     before any device call."""
@@ -627,3 +639,26 @@ def test_mlp_grad_noalloc_argument_errors(sp):
     assert lib.sptrsv_mlp_grad_noalloc(p, p, p, sp.MLP_NOALLOC_MAX_SAMPLES + 1, p, p, None) == 1
     assert "8192" in lib.sptrsv_last_error().decode()
     assert lib.sptrsv_mlp_grad_noalloc(None, p, p, 10, p, p, None) == 1
+
+
+def test_chain_and_sink_queues(sp):
+    """Rows nothing depends on are packed apart from the chain: a diagonal
+    matrix is all sinks, a chain (one row per level, a segment) all chain,
+    and a 2D stencil rewritten into 2-level stages has both (its first-level
+    rows of each stage feed no one after the rewrite)."""
+    d = sp.Plan(*(lambda s: (s.row_ptr, s.col_idx, s.val))(wl.diagonal(5000, seed=1)))
+    assert d.info()["chain_items"] == 0 and d.info()["tiles"] > 0
+    c = sp.Plan(*(lambda s: (s.row_ptr, s.col_idx, s.val))(wl.bidiagonal(3000, seed=1)))
+    assert c.info()["chain_items"] == c.info()["tiles"]
+    s = wl.stencil2d(100, seed=0)
+    p = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", max_width=10**9, max_depth=2, max_fill=12.0)
+    i = p.info()
+    assert 0 < i["chain_items"] < i["tiles"]
+    # the chain rows are exactly the rows some row of L' depends on
+    (lp_ptr, lp_col, _), _ = p.export(with_m=False)
+    rows = np.repeat(np.arange(s.n), np.diff(lp_ptr))
+    needed = np.zeros(s.n, bool)
+    needed[lp_col[lp_col != rows]] = True
+    assert 0 < needed.sum() < s.n
+    for q in (d, c, p):
+        q.close()

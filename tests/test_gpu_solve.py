@@ -211,3 +211,45 @@ def test_graph_replays_match_eager(torch, sp):
         assert np.array_equal(got.view(np.int64), eager.view(np.int64)), rep
     assert plan.check() == 0
     _check_batch(corp, eager)
+
+
+def test_hop_probe(torch, sp):
+    """The hop probe returns a plausible latency for both placements: above
+    the 10 ns clock tick, below a millisecond, and the same-XCD hop is not
+    several times slower than the cross-XCD one."""
+    cross = sp.probe_hop(4000, same_xcd=False)
+    same = sp.probe_hop(4000, same_xcd=True)
+    print("hop ns: cross-XCD", cross, "same-XCD", same, flush=True)
+    for v in (cross, same):
+        assert 10.0 < v < 1e6
+    assert same < 4 * cross
+
+
+@pytest.mark.parametrize("make,pol", [
+    (lambda: wl.stencil3d(40, seed=1), {"max_width": 10**9, "max_depth": 4, "max_fill": 12.0}),
+    (lambda: wl.banded(60000, 200, 8, 24, seed=2), {"max_width": 10**9, "max_depth": 64, "max_fill": 40.0}),
+    (lambda: wl.powerlaw(300000, 3000, seed=3), {"max_width": 4, "max_depth": 256, "max_fill": 1.0}),
+], ids=["stencil3d", "banded", "powerlaw"])
+def test_chain_waves_sweep_bitwise(torch, sp, make, pol):
+    """Chain and sink queues on separate waves: any split of the waves gives
+    the oracle's solution to the gate, and the same bits (each row's sum is
+    fixed by its tile, whichever wave runs it)."""
+    s = make()
+    ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
+    plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", **pol).upload()
+    info = plan.info()
+    assert 0 < info["chain_items"] < info["tiles"]
+    b = torch.from_numpy(s.b).cuda()
+    first = None
+    for cw in (0, 1, 125, 500, 875, 1000):
+        plan.set_chain_share(cw)
+        x = torch.full_like(b, float("nan"))
+        plan.solve(b, x)
+        assert plan.check() == 0
+        got = x.cpu().numpy()
+        print(s.name, "chain share", cw, plan.launch_shape(), relerr(got, ref), flush=True)
+        assert relerr(got, ref) <= TOL
+        if first is None:
+            first = got
+        assert np.array_equal(got, first), cw
+    plan.close()

@@ -6,8 +6,9 @@ starts holds work items that resident waves wait on.  The library caps the
 grid at 8 single-wave workgroups per compute unit and refuses more; this
 test shows, from the gfx950 code object's own resource usage, that 8 fit:
 no scratch memory, at most 256 VGPRs + AGPRs (2 waves on each of the CU's 4
-SIMDs, 512 registers per lane each), and 8 LDS rings within 160 KB even if
-LDS were allocated in 2 KB granules."""
+SIMDs, 512 registers per lane each) and an occupancy of at least 2 waves per
+SIMD in the compiler's own report, and 8 LDS rings within 160 KB even if LDS
+were allocated in 2 KB granules."""
 import os
 import re
 import subprocess
@@ -57,6 +58,9 @@ def test_solve_kernels_prove_eight_waves_per_cu(report):
         regs = r["VGPRs"] + r.get("AGPRs", 0)
         per_simd = 512 // (-(-regs // 8) * 8)
         assert 4 * per_simd >= WAVES_PER_CU, (name, regs)
+        # and the compiler's own figure (it also counts what the register
+        # count alone does not show)
+        assert 4 * r["Occupancy"] >= WAVES_PER_CU, (name, r["Occupancy"])
         lds = -(-r["LDS Size"] // GRANULE) * GRANULE
         assert WAVES_PER_CU * lds <= LDS_BYTES, (name, r["LDS Size"])
 
