@@ -64,12 +64,14 @@ CANDIDATES = {
 }
 DEEPER = {"depth256": "depth512"}
 # Result of the tuning leg on MI355X (used by --no-tune, e.g. under a profiler).
-TUNED = {"stencil3d_128": "depth2", "banded_1m": "depth512", "powerlaw_4m": "paper256",
+TUNED = {"stencil3d_128": "depth4", "banded_1m": "depth512", "powerlaw_4m": "paper256",
          "stencil2d_100": "paper"}
-TUNED_TILING = {"stencil3d_128": 8, "banded_1m": 8, "powerlaw_4m": 2, "stencil2d_100": 4}
+TUNED_TILING = {"stencil3d_128": 4, "banded_1m": 8, "powerlaw_4m": 2, "stencil2d_100": 4}
 TUNED_WAVES = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
 # share of the waves (per mille) serving the chain queue (0 = the library's choice)
-TUNED_CHAIN = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
+TUNED_CHAIN = {"stencil3d_128": 0, "banded_1m": 375, "powerlaw_4m": 0, "stencil2d_100": 0}
+# work queues of the device schedule (2: chain and sinks apart, 1: one queue)
+TUNED_QUEUES = {"stencil3d_128": 2, "banded_1m": 2, "powerlaw_4m": 1, "stencil2d_100": 2}
 CHAIN_CANDIDATES = (125, 250, 375, 500, 625, 750, 875)
 
 
@@ -88,8 +90,8 @@ def kernel_sources_hash() -> str:
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2103_11445_amd", "libsptrsv.so"), "rb") as fh:
         h.update(fh.read())
-    h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n], TUNED_WAVES[n], TUNED_CHAIN[n]]
-                         for n in LARGE}, sort_keys=True).encode())
+    h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n], TUNED_WAVES[n], TUNED_CHAIN[n],
+                             TUNED_QUEUES[n]] for n in LARGE}, sort_keys=True).encode())
     return h.hexdigest()
 
 
@@ -308,16 +310,17 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     # ---- tuning leg
-    plans, chosen, tuning, tiling, waves, chain = {}, {}, {}, {}, {}, {}
+    plans, chosen, tuning, tiling, waves, chain, queues = {}, {}, {}, {}, {}, {}, {}
     for n in names:
         if args.no_tune or args.flush_mb:
             chosen[n] = TUNED.get(n, "paper")
             tiling[n] = TUNED_TILING.get(n, 4)
             waves[n] = TUNED_WAVES.get(n, 0)
             chain[n] = TUNED_CHAIN.get(n, 0)
+            queues[n] = TUNED_QUEUES.get(n, 2)
             plans[n], h = make_plan(n, chosen[n])
-            if tiling[n] != 4:
-                plans[n].set_tiling(tiling[n])
+            if tiling[n] != 4 or queues[n] != 2:
+                plans[n].set_tiling(tiling[n]).set_queues(queues[n])
                 plans[n]._buf = None
                 plans[n].upload()
             plans[n].set_launch(waves[n]).set_chain_share(chain[n])
@@ -396,6 +399,23 @@ def main():
                 if ms < 0.97 * best_ms:
                     best_ms, chain[n] = ms, cw
         plans[n].set_chain_share(chain[n])
+        # one queue of every row in level order instead
+        queues[n] = 2
+        if 0 < i["chain_items"] < i["tiles"]:
+            plans[n].set_queues(1)
+            plans[n]._buf = None
+            plans[n].upload()
+            ms = time_solves(plans[n], n, 2)
+            tuning[n][f"{chosen[n]}/t{tiling[n]}/wpc{waves[n]}/one-queue"] = {
+                "ms": ms, "levels_rw": i["levels_rw"], "entries": tuning[n][chosen[n]]["entries"],
+                "status": plans[n].check()}
+            log(f"[tune] {n} {chosen[n]} one queue: {ms:.3f} ms")
+            if ms < 0.97 * best_ms:
+                best_ms, queues[n] = ms, 1
+            else:
+                plans[n].set_queues(2)
+                plans[n]._buf = None
+                plans[n].upload()
 
     if args.flush_mb:
         # counter runs: every solve starts with the Infinity Cache evicted
@@ -481,7 +501,8 @@ def main():
             "levels_rw": i["levels_rw"], "entries_rw": i["nnz_rw"] + i["nnz_m"],
             "flops": i["flops"], "flops_rw": i["flops_rw"], "bytes": i["bytes"],
             "bytes_rw": i["bytes_rw"], "policy": chosen[n], "terms_per_lane": tiling[n],
-            "waves_per_cu": waves[n], "chain_share": chain[n], "launch_shape": plans[n].launch_shape(),
+            "waves_per_cu": waves[n], "chain_share": chain[n], "queues": queues[n],
+            "launch_shape": plans[n].launch_shape(),
             "chain_items": i["chain_items"], "items": i["tiles"],
             "rhs_mode": i["rhs_mode"], "ms_per_solve": per[n], "ms_per_solve_pct": percentiles(solve_ms[n]),
             "solves_per_s": 1000.0 / per[n],
@@ -521,7 +542,7 @@ def main():
     traffic = None
     if args.workload == "large" and all(chosen[n] == TUNED[n] and tiling[n] == TUNED_TILING[n]
                                         and waves[n] == TUNED_WAVES[n] and chain[n] == TUNED_CHAIN[n]
-                                        for n in names):
+                                        and queues[n] == TUNED_QUEUES[n] for n in names):
         traffic = profiled_traffic()
     if traffic is not None:
         for n in names:
@@ -569,10 +590,12 @@ def main():
 def bench_batched(args, torch, sp, workloads, stream):
     """64 systems of uneven size (n log-uniform in [1e3, 2e5], four families)
     with 1, 4, 8 or 32 right-hand sides each, solved by one graph-captured
-    launch of one batched plan; the rewrite depth, the waves per CU and the
-    row-to-wavefront tiling (terms per lane) are picked by measuring
-    a small grid (the autotuner).  Compared with solving every
-    system separately, column by column, on the plain level-set schedule.
+    launch of one batched plan (the copies of a row for several right-hand
+    sides share one copy of its terms); the rewrite depth, row-to-wavefront
+    tiling, waves per CU, work queues and chain share are picked by measuring
+    (the autotuner).  Compared with the plain union (every system and
+    right-hand side in one launch on the plain level-set schedule, tuned the
+    same way) and with solving every system separately, column by column.
     value = right-hand sides solved per second."""
     corp = workloads.batch_corpus(64)
     ks = [s.b.shape[1] for s in corp]
@@ -606,31 +629,83 @@ def bench_batched(args, torch, sp, workloads, stream):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    # the autotuner: rewrite depth x row-to-wavefront tiling (terms per lane)
-    # x waves per CU, each point measured
-    best, grid = None, {}
-    for cand in ("plain", "depth2", "depth4"):
-        kind, kw = CANDIDATES[cand]
-        t0 = time.perf_counter()
-        plan.rewrite(kind, **kw)
-        t_rw = time.perf_counter() - t0
-        for tpl in (2, 4, 8):
-            plan.set_tiling(tpl)
-            plan._buf = None
-            plan.upload()
-            for wpc in (2, 4):
-                plan.set_launch(wpc)
-                ms = timed(lambda: plan.solve_graph(bcat, x), 2)
-                grid[f"{cand}/t{tpl}/wpc{wpc}"] = round(ms, 4)
-                log(f"[tune] {cand} terms/lane {tpl} wpc {wpc}: {ms:.3f} ms (rewrite {t_rw:.1f} s)")
-                if best is None or ms < best[0]:
-                    best = (ms, cand, tpl, wpc)
-    _, cand, tpl, wpc = best
-    kind, kw = CANDIDATES[cand]
-    plan.rewrite(kind, **kw).set_tiling(tpl)
-    plan._buf = None
-    plan.upload()
-    plan.set_launch(wpc)
+    # the autotuner: each rewrite policy measured on the default launch, then
+    # for the best one and for the plain union (the comparator: every system
+    # and right-hand side in one launch on the plain schedule) the
+    # row-to-wavefront tiling, the waves per CU, the work queues and the
+    # chain's share of the waves, one knob at a time, each point measured
+    grid = {}
+
+    def measure(tag, reps=2):
+        ms = timed(lambda: plan.solve_graph(bcat, x), reps)
+        grid[tag] = round(ms, 4)
+        log(f"[tune] {tag}: {ms:.3f} ms")
+        return ms
+
+    # rewrite policies for the union: its budget of added entries is a
+    # multiple of the union's entries (every right-hand side's copy counted)
+    batch_candidates = {
+        "plain": ("none", {}),
+        "depth4": ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 4.0}),
+        "depth16": ("threshold", {"max_width": INF, "max_depth": 16, "max_fill": 4.0}),
+        "depth64": ("threshold", {"max_width": INF, "max_depth": 64, "max_fill": 4.0}),
+    }
+    current = [None]
+
+    def setup(cand, tpl=4, queues=2):
+        t_rw = 0.0
+        if current[0] != cand:
+            kind, kw = batch_candidates[cand]
+            t0 = time.perf_counter()
+            plan.rewrite(kind, **kw)
+            t_rw = time.perf_counter() - t0
+            current[0] = cand
+        plan.set_tiling(tpl).set_queues(queues)
+        plan._buf = None
+        plan.upload()
+        return t_rw
+
+    def tune(cand):
+        setup(cand)
+        best = (measure(f"{cand}/t4"), 4, 0, 2, 0)
+        for tpl in (2, 8, 16):
+            setup(cand, tpl)
+            ms = measure(f"{cand}/t{tpl}")
+            if ms < best[0]:
+                best = (ms, tpl, 0, 2, 0)
+        setup(cand, best[1])
+        for wpc in (2, 4, 8):
+            plan.set_launch(wpc)
+            ms = measure(f"{cand}/t{best[1]}/wpc{wpc}")
+            if ms < best[0]:
+                best = (ms, best[1], wpc, 2, 0)
+        plan.set_launch(best[2])
+        i = plan.info()
+        if 0 < i["chain_items"] < i["tiles"]:
+            for cw in (250, 500, 750):
+                plan.set_chain_share(cw)
+                ms = measure(f"{cand}/t{best[1]}/wpc{best[2]}/chain{cw}")
+                if ms < best[0]:
+                    best = (ms, best[1], best[2], 2, cw)
+            plan.set_chain_share(0)
+            setup(cand, best[1], 1)
+            plan.set_launch(best[2])
+            ms = measure(f"{cand}/t{best[1]}/wpc{best[2]}/one-queue")
+            if ms < best[0]:
+                best = (ms, best[1], best[2], 1, 0)
+        return best
+
+    screen = {}
+    for cand in batch_candidates:
+        t_rw = setup(cand)
+        screen[cand] = measure(f"{cand}/screen")
+        log(f"[tune] {cand} rewrite {t_rw:.1f} s")
+    best_cand = min((c for c in screen if c != "plain"), key=lambda c: screen[c])
+    plain_best = tune("plain")
+    ms, tpl, wpc, queues, share = tune(best_cand)
+    cand = best_cand
+    setup(cand, tpl, queues)
+    plan.set_launch(wpc).set_chain_share(share)
     for _ in range(args.warmup):
         plan.solve_graph(bcat, x)
     ms = timed(lambda: plan.solve_graph(bcat, x), args.steps)
@@ -645,7 +720,8 @@ def bench_batched(args, torch, sp, workloads, stream):
             errs.append(errors(got[off:off + s_.n * k].reshape(s_.n, k), r_.reshape(s_.n, k)))
             off += s_.n * k
         err = (max(e[0] for e in errs), max(e[1] for e in errs))
-    log(f"[timed] {cand} terms/lane {tpl} wpc {wpc}: {ms:.3f} ms per batch, status {status}, error {err}")
+    log(f"[timed] {cand} terms/lane {tpl} wpc {wpc} queues {queues} chain {share}: {ms:.3f} ms per batch, "
+        f"status {status}, error {err}; plain union {plain_best[0]:.3f} ms")
     # comparator: the plain schedule, one system and one right-hand side at a time
     plain_ms = None
     if not args.no_plain:
@@ -669,7 +745,13 @@ def bench_batched(args, torch, sp, workloads, stream):
         "config": {"workload": "64 systems, n log-uniform [1e3, 2e5], 2D/3D stencil, banded, power-law, "
                                "k in {1,4,8,32} right-hand sides, one graph-captured launch",
                    "rhs_per_step": nrhs, "union_rows": info["n"], "policy": cand, "terms_per_lane": tpl,
-                   "waves_per_cu": wpc},
+                   "waves_per_cu": wpc, "queues": queues, "chain_share": share},
+        "entries_union": info["nnz_rw"], "entries_streamed": info["nnz_streamed"], "nnz_rhs": info["nnz_rhs"],
+        "plain_union_ms": plain_best[0], "plain_union_config": {"terms_per_lane": plain_best[1],
+                                                                 "waves_per_cu": plain_best[2],
+                                                                 "queues": plain_best[3],
+                                                                 "chain_share": plain_best[4]},
+        "speedup_vs_plain_union": plain_best[0] / ms,
         "roofline": {"bound": "hbm", "achieved": info["bytes_rw"] / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": info["bytes_rw"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None},
@@ -679,7 +761,7 @@ def bench_batched(args, torch, sp, workloads, stream):
         "max_rel_err_floored": None if err is None else err[1],
         "levels": info["levels"], "levels_rw": info["levels_rw"],
         "plain_one_at_a_time_ms": plain_ms,
-        "speedup_vs_plain": None if plain_ms is None else plain_ms / ms,
+        "speedup_vs_one_at_a_time": None if plain_ms is None else plain_ms / ms,
         "tuning_ms": grid,
     }
     plan.close()
@@ -744,10 +826,12 @@ def bench_precision(args, torch, sp, workloads, stream):
     plain_ms = timed(lambda: plan.solve(b, x), max(args.plain_steps, 1))
     res["fp64_plain"] = {"ms": plain_ms, "status": plan.check(), "error": errs(x), "levels": plan.info()["levels_rw"]}
     log(f"[precision] FP64 plain: {res['fp64_plain']}")
-    # thin levels of one system are k times wider in the union
-    kind, kw = "threshold", {"max_width": 4 * k, "max_depth": 64, "max_fill": 0.25}
+    # the large workload's tuned power-law plan (thin levels of one system
+    # are k times wider in the union of k copies)
+    kind, kw = CANDIDATES[TUNED["powerlaw_4m"]]
+    kw = {**kw, "max_width": kw["max_width"] * k}
     t0 = time.perf_counter()
-    plan.rewrite(kind, **kw)
+    plan.rewrite(kind, **kw).set_tiling(TUNED_TILING["powerlaw_4m"]).set_queues(TUNED_QUEUES["powerlaw_4m"])
     t_rw = time.perf_counter() - t0
     plan._buf = None
     plan.upload()
@@ -794,6 +878,11 @@ def bench_precision(args, torch, sp, workloads, stream):
         "parity_ok": None if err is None else (err["vs_long_double_floored"] <= 1e-12 and status == 0),
         "legs": res,
         "speedup_vs_plain_fp64": plain_ms / ms,
+        # the rewritten FP64 solve reaches the same accuracy in one pass; the
+        # refined solve needs `iterations` FP32 solves, each bound like it by
+        # the dependency chain, plus the residuals between them
+        "speedup_vs_rewritten_fp64": ms64 / ms,
+        "fp32_solve_over_fp64_solve": ms32 / ms64,
     }
     plan.close()
     torch.cuda.synchronize()

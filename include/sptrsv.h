@@ -277,6 +277,16 @@ sptrsv_status sptrsv_check(sptrsv_plan plan, void *stream, int32_t *device_statu
  * Errors: ARG (negative, or above 8). */
 sptrsv_status sptrsv_set_launch(sptrsv_plan plan, int32_t waves_per_cu);
 
+/* Work queues of the device schedule.  2 (the default): rows that some
+ * other row depends on (the chain) and rows nothing depends on (sinks) are
+ * packed into separate tiles, the chain's tiles and segments forming one
+ * queue and the sinks' tiles another, each in level order, served by
+ * separate waves (see sptrsv_set_chain_share), so sinks never hold up the
+ * dependency chain.  1: every row in one queue, in level order.  Repacks
+ * the host image (the upload becomes stale); the schedule and the rewrite
+ * are unchanged.  Errors: ARG (not 1 or 2), OVERFLOW, OOM. */
+sptrsv_status sptrsv_set_queues(sptrsv_plan plan, int32_t queues);
+
 /* Share of the solve grid's waves, in per mille, that serves the chain
  * queue (rows that some other row depends on, in level order); the others
  * serve the sink queue (rows nothing depends on: their time is bandwidth,
@@ -306,9 +316,9 @@ sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks);
  * bytes for FP64, 4 for FP32): 4 + v per stored entry (int32 column + value,
  * diagonals included) + 8 + 2v per row (row offset, row id, b_i, x_i);
  * gathers of x and b are counted as cache hits.  bytes_rw counts the entries
- * of L' and those the right-hand-side step reads (nnz_rhs), plus 2v per row
- * for the M pass (b' written and read) or 8 + 2v per row for the stage
- * solve. */
+ * of L' the solve reads (nnz_streamed) and those the right-hand-side step
+ * reads (nnz_rhs), plus 2v per row for the M pass (b' written and read) or
+ * 8 + 2v per row for the stage solve. */
 typedef struct {
     int32_t n;
     int32_t levels;      /* levels of L */
@@ -329,7 +339,8 @@ typedef struct {
                             wave executes in order) */
     int32_t rhs_mode;    /* right-hand-side step in use: 0 none (no b-terms),
                             SPTRSV_RHS_MPASS or SPTRSV_RHS_STAGE */
-    int64_t nnz_rhs;     /* entries it reads: nnz(M), or nnz(L_B) */
+    int64_t nnz_rhs;     /* entries it reads: nnz(M), or the entries of L_B
+                            its solve reads */
     int32_t rhs_segments;/* stage solve: stages solved whole by one wave each
                             (no wait on another wave); the others run level
                             by level across the grid */
@@ -345,6 +356,10 @@ typedef struct {
                             depends on (the chain queue); the other
                             tiles - chain_items hold only rows nothing
                             depends on (the sink queue) */
+    int64_t nnz_streamed;/* entries of L' a solve reads: nnz_rw, less the
+                            terms of the copies of a batched plan's rows
+                            that read copy 0's (power-of-two k <= 64
+                            right-hand sides share one copy of the terms) */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

@@ -62,7 +62,7 @@ class _Info(ctypes.Structure):
                 ("rhs_mode", ctypes.c_int32), ("nnz_rhs", ctypes.c_int64),
                 ("rhs_segments", ctypes.c_int32), ("reg_chunks", ctypes.c_int32),
                 ("segments", ctypes.c_int32), ("ring_segments", ctypes.c_int32),
-                ("chain_items", ctypes.c_int64)]
+                ("chain_items", ctypes.c_int64), ("nnz_streamed", ctypes.c_int64)]
 
 
 _lib = None
@@ -111,6 +111,7 @@ def load():
         "sptrsv_set_wait_limit": (S, [P, U64]),
         "sptrsv_set_launch": (S, [P, I32]),
         "sptrsv_set_chain_share": (S, [P, I32]),
+        "sptrsv_set_queues": (S, [P, I32]),
         "sptrsv_launch_shape": (S, [P, P, P]),
         "sptrsv_plan_info": (S, [P, P]),
         "sptrsv_plan_levels": (S, [P, I32, P]),
@@ -246,6 +247,12 @@ class Plan:
 
     def set_launch(self, waves_per_cu: int = 0):
         _check(load().sptrsv_set_launch(self._h, int(waves_per_cu)))
+        return self
+
+    def set_queues(self, queues: int = 2) -> "Plan":
+        """Work queues of the device schedule: 2 (chain and sinks apart) or
+        1 (every row in level order); repacks."""
+        _check(load().sptrsv_set_queues(self._h, int(queues)))
         return self
 
     def set_chain_share(self, per_mille: int = 0):

@@ -360,6 +360,26 @@ sptrsv_status sptrsv_set_tiling(sptrsv_plan plan, int32_t terms_per_lane) {
     });
 }
 
+sptrsv_status sptrsv_set_queues(sptrsv_plan plan, int32_t queues) {
+    return guarded([&]() -> sptrsv_status {
+        if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
+        if (queues != 1 && queues != 2) return set_err(SPTRSV_ERR_ARG, "queues must be 1 or 2");
+        if (queues == plan->queues) return SPTRSV_OK;
+        const int old = plan->queues;
+        plan->queues = queues;
+        plan->uploaded = false;
+        drop_graph(*plan);
+        try {
+            sptrsv::pack(*plan);
+        } catch (...) {
+            plan->queues = old;
+            sptrsv::pack(*plan);
+            throw;
+        }
+        return SPTRSV_OK;
+    });
+}
+
 sptrsv_status sptrsv_set_rhs_mode(sptrsv_plan plan, int32_t mode) {
     return guarded([&]() -> sptrsv_status {
         if (!plan) return set_err(SPTRSV_ERR_ARG, "plan is NULL");
@@ -494,7 +514,8 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->nnz_rhs = p.layout.nnz_rhs;
     // the solve of L' plus the right-hand-side step: M entries and b, b' per
     // row (M pass), or a whole solve of L_B (stage solves)
-    o->bytes_rw = (4 + vb) * (o->nnz_rw + o->nnz_rhs) + (8 + 2 * vb) * (int64_t)p.n;
+    o->nnz_streamed = p.nnz_streamed;
+    o->bytes_rw = (4 + vb) * (o->nnz_streamed + o->nnz_rhs) + (8 + 2 * vb) * (int64_t)p.n;
     if (p.layout.rhs_mode == sptrsv::kRhsMPass) o->bytes_rw += 2 * vb * (int64_t)p.n;
     if (p.layout.rhs_mode == sptrsv::kRhsStage) o->bytes_rw += (8 + 2 * vb) * (int64_t)p.n;
     o->device_bytes = (int64_t)p.layout.total;

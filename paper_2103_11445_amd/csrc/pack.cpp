@@ -55,6 +55,7 @@ namespace sptrsv {
 namespace {
 
 constexpr int kBins = 7;  // g = 1, 2, 4, ..., 64
+constexpr int kKinds = 7;  // copies per row: 1, 2, 4, ..., 64
 constexpr int32_t kPad = INT32_MIN;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -126,12 +127,17 @@ void pack(Plan &p) {
             sub->terms_per_lane = p.terms_per_lane;
             analyse(*sub, n, brp.data(), bci.data(), bval.data());
             sub->upper = p.upper;
+            // the stage system of a batched plan holds the same copies
+            sub->batch_count = p.batch_count;
+            sub->sys_n = p.sys_n;
+            sub->sys_k = p.sys_k;
+            sub->sys_base = p.sys_base;
             sub->comp.resize((size_t)n);
             for (int32_t i = 0; i < n; ++i) sub->comp[(size_t)i] = p.stage_of_level[(size_t)p.level[(size_t)i]];
             sptrsv_policy none{};
             none.kind = SPTRSV_POLICY_NONE;
             rewrite(*sub, none);  // packs the stage system's image
-            nnz_rhs = (int64_t)bci.size();
+            nnz_rhs = sub->nnz_streamed;
             p.sub = std::move(sub);
         } else {
             nnz_rhs = (int64_t)p.m_col.size();
@@ -163,47 +169,83 @@ void pack(Plan &p) {
 
     // ---- order rows and cut items
     std::vector<int32_t> slot_row((size_t)n);
-    struct Tile { int64_t chunk_off; int32_t row_off, nch, nrows, lg; };
+    // a wide tile: its chunks, slots, rows, lanes per row (2^lg) and, for rows
+    // that are copies of one row for several right-hand sides (a batched
+    // plan), 2^lgk copies per row with the first row's copy index c0
+    struct Tile { int64_t chunk_off; int32_t row_off, nch, nrows, lg, lgk = 0, c0 = 0; };
     struct SegTile { int32_t row_off, nrows, lg, level; };
     struct Item { int kind; int64_t a, b; int32_t level; };  // wide: a = wide tile; seg: a = first seg tile, b = count
     std::vector<Tile> tiles;
     std::vector<SegTile> stiles;
     std::vector<Item> items, sink_items;  // the chain queue, the sink queue
     // rows of L' that another row of L' depends on
-    std::vector<char> needed((size_t)n, 0);
-    for (int32_t i = 0; i < n; ++i)
-        for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q)
-            needed[(size_t)p.lp_col[(size_t)q]] = 1;
+    // (with one queue every row counts as needed: all go to the first queue)
+    std::vector<char> needed((size_t)n, p.queues == 1 ? 1 : 0);
+    if (p.queues != 1)
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q)
+                needed[(size_t)p.lp_col[(size_t)q]] = 1;
     std::vector<int32_t> seg_of_slot((size_t)n, -1);   // segment id of each slot
+    // copies per row (log2) where a batched plan holds a power-of-two k <= 64
+    // copies of each row of a system (0 otherwise: each row its own terms),
+    // and the copy index of each row
+    std::vector<int8_t> copies_lg((size_t)n, 0);
+    std::vector<int32_t> copy_of((size_t)n, 0);
+    for (size_t j = 0; j < p.sys_k.size(); ++j) {
+        const int32_t kj = p.sys_k[j];
+        if (kj <= 1 || kj > 64 || (kj & (kj - 1)) || p.upper) continue;
+        int lgk = 0;
+        while ((1 << lgk) < kj) ++lgk;
+        const int64_t b0 = p.sys_base[j], b1 = b0 + (int64_t)p.sys_n[j] * kj;
+        for (int64_t u = b0; u < b1; ++u) {
+            copies_lg[(size_t)u] = (int8_t)lgk;
+            copy_of[(size_t)u] = (int32_t)((u - b0) & (kj - 1));
+        }
+    }
     int64_t nchunks = 0;
     int32_t slot = 0, nseg = 0;
 
-    // rows[0, count) of level l (ascending) as wide tiles, binned by length,
-    // appended to the chain queue or, for sinks, to the sink queue
+    // rows[0, count) of level l (ascending) as wide tiles, binned by length
+    // and by copies per row, appended to the chain queue or, for sinks, to
+    // the sink queue.  The copies of a row (same level, length and
+    // dependents) are consecutive in a bin, so copy c of a row sits c slots
+    // after copy 0 and its terms are copy 0's shifted by c slots: a tile
+    // stores the terms of copy 0 only, and the lanes of copy c add c.
+    auto bin2 = [&](int32_t r) { return bin_of(len[(size_t)r], p.terms_per_lane) * kKinds + copies_lg[(size_t)r]; };
     auto wide_tiles = [&](const int32_t *rows, int32_t count, int32_t l, bool sink) {
-        int32_t cnt[kBins] = {0};
-        for (int32_t q = 0; q < count; ++q) ++cnt[bin_of(len[(size_t)rows[q]], p.terms_per_lane)];
-        int32_t start[kBins];
+        int32_t cnt[kBins * kKinds] = {0};
+        for (int32_t q = 0; q < count; ++q) ++cnt[bin2(rows[q])];
+        int32_t start[kBins * kKinds];
         int32_t acc = slot;
-        for (int g = 0; g < kBins; ++g) {
-            start[g] = acc;
-            acc += cnt[g];
+        for (int b = 0; b < kBins * kKinds; ++b) {
+            start[b] = acc;
+            acc += cnt[b];
         }
-        int32_t cur[kBins];
-        std::copy(start, start + kBins, cur);
+        int32_t cur[kBins * kKinds];
+        std::copy(start, start + kBins * kKinds, cur);
         for (int32_t q = 0; q < count; ++q) {
             const int32_t r = rows[q];
-            slot_row[(size_t)cur[bin_of(len[(size_t)r], p.terms_per_lane)]++] = r;
+            slot_row[(size_t)cur[bin2(r)]++] = r;
         }
-        for (int g = 0; g < kBins; ++g) {
+        for (int b = 0; b < kBins * kKinds; ++b) {
+            const int g = b / kKinds, lgk = b % kKinds;
             const int32_t per = 64 >> g;
-            for (int32_t s = start[g]; s < start[g] + cnt[g]; s += per) {
-                const int32_t nr = std::min(per, start[g] + cnt[g] - s);
+            int64_t group_chunks = 0;  // chunks of the tile holding copy 0 of the current row
+            for (int32_t s = start[b]; s < start[b] + cnt[b]; s += per) {
+                const int32_t nr = std::min(per, start[b] + cnt[b] - s);
                 int64_t mx = 0;
                 for (int32_t r = 0; r < nr; ++r) mx = std::max(mx, len[(size_t)slot_row[(size_t)(s + r)]]);
                 const int64_t nch = (mx + (1 << g) - 1) >> g;
+                const int32_t c0 = copy_of[(size_t)slot_row[(size_t)s]];
                 (sink ? sink_items : items).push_back({0, (int64_t)tiles.size(), 0, l});
-                tiles.push_back({nchunks, s, (int32_t)nch, nr, g});
+                if (lgk > 0 && c0 > 0) {
+                    // later copies of one row (more copies than rows per
+                    // tile): read the terms of the tile with copy 0
+                    tiles.push_back({group_chunks, s, (int32_t)nch, nr, g, lgk, c0});
+                    continue;
+                }
+                group_chunks = nchunks;
+                tiles.push_back({nchunks, s, (int32_t)nch, nr, g, lgk, c0});
                 nchunks += nch;
             }
         }
@@ -508,6 +550,7 @@ void pack(Plan &p) {
     };
 
     int32_t sid = -1;
+    int64_t shared_skip = 0;  // off-diagonal terms of copies that read copy 0's
     bool all_ring = true;
     int32_t ring_count = 0;
     for (size_t it = 0; it < items.size(); ++it) {
@@ -554,14 +597,21 @@ void pack(Plan &p) {
         desc[4 * it + 0] = (int32_t)T.chunk_off;
         desc[4 * it + 1] = T.row_off;
         desc[4 * it + 2] = T.nch;
-        desc[4 * it + 3] = (T.nrows << 8) | T.lg;
+        desc[4 * it + 3] = (T.nrows << 16) | (T.c0 << 8) | (T.lgk << 4) | T.lg;
         const int32_t g = 1 << T.lg;
-        for (int32_t r = 0; r < T.nrows; ++r) {
-            const int32_t i = slot_row[(size_t)(T.row_off + r)];
+        for (int32_t r = 0; r < T.nrows; ++r)
+            if ((r & ((1 << T.lgk) - 1)) || T.c0 > 0) shared_skip += len[(size_t)slot_row[(size_t)(T.row_off + r)]];
+        if (T.c0 > 0) continue;  // its terms are those of the tile with copy 0
+        // one row of terms per 2^lgk copies: the first copy of each group
+        // (or of the tile, when a group spans tiles), its columns moved back
+        // by its copy index to those of copy 0
+        for (int32_t r0 = 0; r0 < std::max(1, T.nrows >> T.lgk); ++r0) {
+            const int32_t i = slot_row[(size_t)(T.row_off + (r0 << T.lgk))];
+            const int32_t c = copy_of[(size_t)i];
             int64_t t_ = 0;
             row_terms(i, -1, 0, [&](int32_t col, double v) {
-                const int64_t idx = (T.chunk_off + (t_ >> T.lg)) * 64 + r * g + (t_ & (g - 1));
-                tcol[idx] = col;
+                const int64_t idx = (T.chunk_off + (t_ >> T.lg)) * 64 + r0 * g + (t_ & (g - 1));
+                tcol[idx] = col - c;
                 putv(Ly.tval, idx, v);
                 ++t_;
             });
@@ -630,6 +680,7 @@ void pack(Plan &p) {
     for (size_t st = 0; st < stiles.size(); ++st) p.stamp_level[items.size() + st] = stiles[st].level;
     p.ntiles = (int64_t)items.size();
     p.nchain = nchain;
+    p.nnz_streamed = (p.lp_ptr.empty() ? 0 : p.lp_ptr.back()) - shared_skip;
     p.nchunks = nchunks;
     p.nseg = nseg;
     p.nseg_tiles = nst;

@@ -71,7 +71,8 @@ struct Layout {
     size_t sub = 0;               // kRhsStage: offset of the stage system's image
     const Layout *sub_layout = nullptr;
     size_t workspace = 0;  // Workspace block
-    size_t tiles = 0;      // int4[nitems]: wide tile {chunk_off, row_off, nchunks, nrows<<8 | log2 lanes}
+    size_t tiles = 0;      // int4[nitems]: wide tile {chunk_off, row_off, nchunks,
+                           //   nrows<<16 | first copy<<8 | log2 copies<<4 | log2 lanes}
                            //   or segment {first segment tile, count, 0, 1<<31}
     size_t rows = 0;       // int32[n]      row id of each packed slot
     size_t diag = 0;       // double[n]     diagonal of each packed slot
@@ -141,6 +142,9 @@ struct Plan {
     // row-to-wavefront tiling: a row of len terms gets the smallest power of
     // two g of lanes with len <= terms_per_lane * g (capped at 64)
     int terms_per_lane = 4;
+    // work queues of the device schedule: 2 = chain and sinks apart, 1 = one
+    // queue of every row in level order
+    int queues = 2;
     std::unique_ptr<struct Plan> sub;
     bool is_sub = false;  // a stage system (no residual data, no sub-plan)
     // a stage system's stage of each row: its diagonal blocks are
@@ -170,6 +174,7 @@ struct Plan {
     int64_t ntiles = 0;      // work items (wide tiles and segments)
     int64_t nchain = 0;      // of which the chain queue (the rest hold only rows nothing depends on)
     int64_t chain_work = 0, sink_work = 0;  // 64-lane chunks plus rows packed in each queue
+    int64_t nnz_streamed = 0;  // entries of L' the image holds (copies sharing terms count once)
     int64_t nchunks = 0;
     int32_t nseg = 0;        // segments
     int64_t nseg_tiles = 0;  // tiles inside segments

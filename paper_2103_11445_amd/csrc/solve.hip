@@ -374,13 +374,29 @@ struct Tile {
     T diag;
 };
 
-__device__ inline bool tile_active(const int4 d, int lane) { return (lane >> (d.w & 0xff)) < (d.w >> 8); }
+// Descriptor word of a wide tile: rows << 16 | first copy << 8 | log2 copies
+// per row << 4 | log2 lanes per row.  Rows that are copies of one row (a
+// batched plan's right-hand sides) share copy 0's terms: the lanes of copy c
+// read them and gather c slots further.
+__device__ inline int tile_lg(const int4 d) { return d.w & 0xf; }
+__device__ inline int tile_lgk(const int4 d) { return (d.w >> 4) & 0xf; }
+__device__ inline int tile_rows(const int4 d) { return d.w >> 16; }
+__device__ inline bool tile_active(const int4 d, int lane) { return (lane >> tile_lg(d)) < tile_rows(d); }
 __device__ inline bool tile_lead(const int4 d, int lane) {
-    return tile_active(d, lane) && (lane & ((1 << (d.w & 0xff)) - 1)) == 0;
+    return tile_active(d, lane) && (lane & ((1 << tile_lg(d)) - 1)) == 0;
+}
+// where the lane's terms are stored within a chunk, and its copy index
+__device__ inline int tile_term_lane(const int4 d, int lane) {
+    const int lg = tile_lg(d);
+    return (((lane >> lg) >> tile_lgk(d)) << lg) | (lane & ((1 << lg) - 1));
+}
+__device__ inline int32_t tile_copy(const int4 d, int lane) {
+    return (((d.w >> 8) & 0xff) + (lane >> tile_lg(d))) & ((1 << tile_lgk(d)) - 1);
 }
 template <typename V, int kReg>
 __device__ inline int32_t tile_col(const Tile<V, kReg> &T, int c, int lane) {
-    return tile_active(T.d, lane) && c < T.d.z ? T.col[c] : kPad;
+    const int32_t k = T.col[c];
+    return tile_active(T.d, lane) && c < T.d.z && k != kPad ? k + tile_copy(T.d, lane) : kPad;
 }
 template <typename V, int kReg>
 __device__ inline V tile_val(const Tile<V, kReg> &T, int c, int lane) {
@@ -391,14 +407,14 @@ template <typename V, int kReg>
 __device__ inline void load_tile(const SolveArgs<V> &a, const int4 d, int lane, Tile<V, kReg> &T) {
     T.d = d;
     const bool active = tile_active(d, lane);
-    const size_t base = (size_t)d.x * 64 + lane;
+    const size_t base = (size_t)d.x * 64 + tile_term_lane(d, lane);
 #pragma unroll
     for (int c = 0; c < kReg; ++c) {
         const bool ok = active && c < d.z;
         T.col[c] = *(ok ? a.tcol + base + (size_t)c * 64 : a.rows);
         T.val[c] = *(ok ? a.tval + base + (size_t)c * 64 : a.diag);
     }
-    const int32_t slot = tile_lead(d, lane) ? d.y + (lane >> (d.w & 0xff)) : 0;
+    const int32_t slot = tile_lead(d, lane) ? d.y + (lane >> tile_lg(d)) : 0;
     T.row = a.rows[slot];
     T.diag = a.diag[slot];
 }
@@ -604,7 +620,8 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         //    lanes read their own pad slot and count as kPad)
         for (int c0 = kReg; c0 < cur.d.z; c0 += kReg) {
             const bool act = tile_active(cur.d, lane);
-            const size_t base = (size_t)cur.d.x * 64 + lane;
+            const size_t base = (size_t)cur.d.x * 64 + tile_term_lane(cur.d, lane);
+            const int32_t copy = tile_copy(cur.d, lane);
             int32_t kc[kReg];
             T vc[kReg];
             typename Val<T>::Bits gc[kReg];
@@ -616,7 +633,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
             }
 #pragma unroll
             for (int u = 0; u < kReg; ++u) {
-                if (!act || c0 + u >= cur.d.z) kc[u] = kPad;
+                kc[u] = !act || c0 + u >= cur.d.z || kc[u] == kPad ? kPad : kc[u] + copy;
                 gc[u] = gather_x(a, kc[u]);
             }
             resolve_pending<kReg, true>(a, kc, gc);
@@ -624,11 +641,11 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
             for (int u = 0; u < kReg; ++u) acc = fma(vc[u], term_value<T>(kc[u], gc[u]), acc);
         }
         // 5. row sums across the row's lanes, then x_i
-        acc = group_sum(acc, cur.d.w & 0xff);
+        acc = group_sum(acc, tile_lg(cur.d));
         if (lead) {
             const T bi = a.bscale ? braw * cur.diag : braw;
             const T xi = (bi + acc) / cur.diag;
-            __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + cur.d.y + (lane >> (cur.d.w & 0xff)),
+            __hip_atomic_store(reinterpret_cast<typename Val<T>::Bits *>(a.x) + cur.d.y + (lane >> tile_lg(cur.d)),
                                Val<T>::bits(xi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             a.xout[cur.row] = xi;
         }

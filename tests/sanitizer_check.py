@@ -43,7 +43,7 @@ def main() -> int:
             o = os.path.join(tmp, src + ".o")
             run([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
             objs.append(o)
-        lib = os.path.join(tmp, "libsptrsv_san.so")
+        lib = os.path.join(tmp, "libsptrsv.so")  # the C program test links -lsptrsv from its folder
         run(["g++", "-shared", "-fPIC", *SAN, "-o", lib, *objs, f"-L{ROCM}/lib", "-lamdhip64", "-lpthread",
              f"-Wl,-rpath,{ROCM}/lib"])
         olib = os.path.join(tmp, "liboracle_san.so")

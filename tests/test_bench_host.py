@@ -30,6 +30,7 @@ def test_recorded_tuning_is_buildable():
         assert b.TUNED_TILING[name] in (2, 4, 8, 16)
         assert b.TUNED_WAVES[name] in (0, 2, 4, 8)
         assert b.TUNED_CHAIN[name] in (0,) + b.CHAIN_CANDIDATES
+        assert b.TUNED_QUEUES[name] in (1, 2)
     for shallow, deep in b.DEEPER.items():
         assert shallow in b.CANDIDATES and deep in b.CANDIDATES
         assert b.CANDIDATES[deep][1]["max_depth"] > b.CANDIDATES[shallow][1]["max_depth"]

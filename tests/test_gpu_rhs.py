@@ -132,3 +132,35 @@ def test_tilings_match_oracle(torch, sp, make, tpl):
     err = errors(x.cpu().numpy(), ref)
     print(s.name, tpl, plan.info()["tiles"], plan.info()["reg_chunks"], err, flush=True)
     assert err[1] <= TOL
+
+
+@pytest.mark.parametrize("tpl", [1, 4, 16])
+@pytest.mark.parametrize("kind,kw", [
+    ("none", {}),
+    ("threshold", {"max_width": 10**9, "max_depth": 4, "max_fill": 10.0}),
+    ("threshold", {"max_width": 10**9, "max_depth": 64, "max_fill": 40.0}),
+], ids=["plain", "depth4", "depth64"])
+def test_shared_copy_terms(torch, sp, tpl, kind, kw):
+    """Batched systems with 2, 5, 16 and 64 right-hand sides: the copies of a
+    row (power-of-two k) share copy 0's terms in the tiles, whether a row's
+    copies share a tile (k below the rows per tile) or one row's copies span
+    several tiles (k above it); k = 5 keeps a copy of the terms per row.
+    Every column against the oracle."""
+    corp = wl.batch_corpus(8, nmin=300, nmax=15000, ks=(2, 5, 16, 64), seed=60)
+    ks = [c.b.shape[1] for c in corp]
+    assert {2, 5, 16, 64} <= set(ks)
+    plan = sp.Plan.batch([(c.row_ptr, c.col_idx, c.val) for c in corp], ks)
+    plan.rewrite(kind, **kw).set_tiling(tpl).upload()
+    b = torch.from_numpy(np.concatenate([c.b.reshape(-1) for c in corp])).cuda()
+    x = torch.full_like(b, float("nan"))
+    plan.solve(b, x)
+    assert plan.check() == 0
+    got, off = x.cpu().numpy(), 0
+    for c in corp:
+        k = c.b.shape[1]
+        ref = oracle.solve(c.row_ptr, c.col_idx, c.val, c.b)
+        err = errors(got[off:off + c.n * k].reshape(c.n, k), ref)
+        print(c.name, k, tpl, kind, kw.get("max_depth"), plan.info()["rhs_mode"], err, flush=True)
+        assert err[1] <= TOL, (c.name, k)
+        off += c.n * k
+    plan.close()

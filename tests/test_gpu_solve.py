@@ -231,9 +231,10 @@ def test_hop_probe(torch, sp):
     (lambda: wl.powerlaw(300000, 3000, seed=3), {"max_width": 4, "max_depth": 256, "max_fill": 1.0}),
 ], ids=["stencil3d", "banded", "powerlaw"])
 def test_chain_waves_sweep_bitwise(torch, sp, make, pol):
-    """Chain and sink queues on separate waves: any split of the waves gives
-    the oracle's solution to the gate, and the same bits (each row's sum is
-    fixed by its tile, whichever wave runs it)."""
+    """Chain and sink queues on separate waves: any split of the waves, and
+    one queue of every row in level order, give the oracle's solution to the
+    gate and the same bits (each row's summation order is fixed by its
+    length and the tiling, whichever tile and wave run it)."""
     s = make()
     ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
     plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", **pol).upload()
@@ -241,13 +242,17 @@ def test_chain_waves_sweep_bitwise(torch, sp, make, pol):
     assert 0 < info["chain_items"] < info["tiles"]
     b = torch.from_numpy(s.b).cuda()
     first = None
-    for cw in (0, 1, 125, 500, 875, 1000):
+    for q, cw in ((2, 0), (2, 1), (2, 125), (2, 500), (2, 875), (2, 1000), (1, 0)):
+        if q == 1:
+            plan.set_queues(1)
+            plan._buf = None
+            plan.upload()
         plan.set_chain_share(cw)
         x = torch.full_like(b, float("nan"))
         plan.solve(b, x)
         assert plan.check() == 0
         got = x.cpu().numpy()
-        print(s.name, "chain share", cw, plan.launch_shape(), relerr(got, ref), flush=True)
+        print(s.name, "queues", q, "chain share", cw, plan.launch_shape(), relerr(got, ref), flush=True)
         assert relerr(got, ref) <= TOL
         if first is None:
             first = got
