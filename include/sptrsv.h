@@ -360,6 +360,13 @@ typedef struct {
                             terms of the copies of a batched plan's rows
                             that read copy 0's (power-of-two k <= 64
                             right-hand sides share one copy of the terms) */
+    int32_t m_stored;    /* 1 if the plan holds M's entries.  The rewrite
+                            stores them only when the right-hand-side step
+                            reads them (the M pass); a plan that solves the
+                            stage system instead keeps only M's row counts,
+                            and sptrsv_plan_export or a switch to the M pass
+                            builds the entries then (as long as the rewrite
+                            itself, same values) */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 
@@ -380,7 +387,10 @@ sptrsv_status sptrsv_plan_schedule(sptrsv_plan plan, int32_t *level_ptr, int32_t
  * L' = (lp_ptr int64[n+1], lp_col int32[nnz_rw], lp_val double[nnz_rw]) with
  * ascending columns and the diagonal last, and M = (m_ptr int64[n+1],
  * m_col int32[nnz_m], m_val double[nnz_m]) with ascending columns.  With
- * m_ptr NULL only L' is written (M can be far larger).  Errors: ARG. */
+ * m_ptr NULL only L' is written (M can be far larger).  A plan that does not
+ * hold M's entries (sptrsv_info.m_stored 0) builds them first: host time and
+ * memory of the order of the rewrite; the device image is unchanged.
+ * Errors: ARG, OOM. */
 sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_col,
                                  double *lp_val, int64_t *m_ptr, int32_t *m_col,
                                  double *m_val);

@@ -62,7 +62,8 @@ class _Info(ctypes.Structure):
                 ("rhs_mode", ctypes.c_int32), ("nnz_rhs", ctypes.c_int64),
                 ("rhs_segments", ctypes.c_int32), ("reg_chunks", ctypes.c_int32),
                 ("segments", ctypes.c_int32), ("ring_segments", ctypes.c_int32),
-                ("chain_items", ctypes.c_int64), ("nnz_streamed", ctypes.c_int64)]
+                ("chain_items", ctypes.c_int64), ("nnz_streamed", ctypes.c_int64),
+                ("m_stored", ctypes.c_int32)]
 
 
 _lib = None

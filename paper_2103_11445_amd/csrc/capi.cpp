@@ -505,7 +505,7 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->levels_rw = p.nlev_rw;
     o->nnz = p.n ? p.rp[(size_t)p.n] : 0;
     o->nnz_rw = p.lp_ptr.empty() ? 0 : p.lp_ptr.back();
-    o->nnz_m = p.m_ptr.empty() ? 0 : p.m_ptr.back();
+    o->nnz_m = p.nnz_m();
     o->flops = 2 * (o->nnz - p.n) + p.n;
     o->flops_rw = 2 * (o->nnz_rw - p.n + o->nnz_m) + p.n;
     const int64_t vb = p.precision / 8;
@@ -527,6 +527,7 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->segments = p.nseg;
     o->ring_segments = p.ring_segs;
     o->chain_items = p.nchain;
+    o->m_stored = p.m_kept ? 1 : 0;
     return SPTRSV_OK;
 }
 
@@ -554,18 +555,21 @@ sptrsv_status sptrsv_plan_schedule(sptrsv_plan plan, int32_t *level_ptr, int32_t
 
 sptrsv_status sptrsv_plan_export(sptrsv_plan plan, int64_t *lp_ptr, int32_t *lp_col, double *lp_val,
                                  int64_t *m_ptr, int32_t *m_col, double *m_val) {
-    if (!plan || !lp_ptr) return set_err(SPTRSV_ERR_ARG, "null argument");
-    const sptrsv::Plan &p = *plan;
-    if ((!lp_col || !lp_val) && !p.lp_col.empty()) return set_err(SPTRSV_ERR_ARG, "null L' arrays");
-    std::copy(p.lp_ptr.begin(), p.lp_ptr.end(), lp_ptr);
-    std::copy(p.lp_col.begin(), p.lp_col.end(), lp_col);
-    std::copy(p.lp_val.begin(), p.lp_val.end(), lp_val);
-    if (!m_ptr) return SPTRSV_OK;  // L' only
-    if ((!m_col || !m_val) && !p.m_col.empty()) return set_err(SPTRSV_ERR_ARG, "null M arrays");
-    std::copy(p.m_ptr.begin(), p.m_ptr.end(), m_ptr);
-    std::copy(p.m_col.begin(), p.m_col.end(), m_col);
-    std::copy(p.m_val.begin(), p.m_val.end(), m_val);
-    return SPTRSV_OK;
+    return guarded([&]() -> sptrsv_status {
+        if (!plan || !lp_ptr) return set_err(SPTRSV_ERR_ARG, "null argument");
+        sptrsv::Plan &p = *plan;
+        if ((!lp_col || !lp_val) && !p.lp_col.empty()) return set_err(SPTRSV_ERR_ARG, "null L' arrays");
+        if (m_ptr && (!m_col || !m_val) && p.nnz_m() > 0) return set_err(SPTRSV_ERR_ARG, "null M arrays");
+        if (m_ptr) sptrsv::materialise_m(p);
+        std::copy(p.lp_ptr.begin(), p.lp_ptr.end(), lp_ptr);
+        std::copy(p.lp_col.begin(), p.lp_col.end(), lp_col);
+        std::copy(p.lp_val.begin(), p.lp_val.end(), lp_val);
+        if (!m_ptr) return SPTRSV_OK;  // L' only
+        std::copy(p.m_ptr.begin(), p.m_ptr.end(), m_ptr);
+        std::copy(p.m_col.begin(), p.m_col.end(), m_col);
+        std::copy(p.m_val.begin(), p.m_val.end(), m_val);
+        return SPTRSV_OK;
+    });
 }
 
 sptrsv_status sptrsv_solve_stamped(sptrsv_plan plan, const double *b, double *x, uint64_t *stamps, void *stream) {

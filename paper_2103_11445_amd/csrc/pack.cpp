@@ -95,13 +95,23 @@ static void stage_system(const Plan &p, std::vector<int32_t> &rp, std::vector<in
     }
 }
 
+int64_t stage_system_nnz(const Plan &p) {
+    int64_t c = 0;
+    for (int32_t i = 0; i < p.n; ++i) {
+        const int32_t si = p.stage_of_level[(size_t)p.level[(size_t)i]];
+        for (int32_t q = p.rp[(size_t)i]; q < p.rp[(size_t)i + 1]; ++q)
+            c += p.stage_of_level[(size_t)p.level[(size_t)p.ci[(size_t)q]]] == si;
+    }
+    return c;
+}
+
 // Choice of the right-hand-side step: none without b-terms; else as
 // requested, or the stage solves when M holds more than twice the entries
 // of L_B (its bytes then dominate the M pass).
-static int32_t choose_rhs(const Plan &p, int64_t nnz_b) {
-    if (p.m_col.empty() || p.is_sub) return kRhsNone;
+int32_t choose_rhs(const Plan &p, int64_t nnz_m, int64_t nnz_b) {
+    if (nnz_m == 0 || p.is_sub) return kRhsNone;
     if (p.rhs_request == kRhsMPass || p.rhs_request == kRhsStage) return p.rhs_request;
-    return (int64_t)p.m_col.size() > 2 * nnz_b ? kRhsStage : kRhsMPass;
+    return nnz_m > 2 * nnz_b ? kRhsStage : kRhsMPass;
 }
 
 void pack(Plan &p) {
@@ -115,11 +125,12 @@ void pack(Plan &p) {
     int32_t rhs_mode = kRhsNone;
     int64_t nnz_rhs = 0;
     p.sub.reset();
-    if (!p.m_col.empty() && !p.is_sub) {
+    if (p.nnz_m() > 0 && !p.is_sub) {
         std::vector<int32_t> brp, bci;
         std::vector<double> bval;
         stage_system(p, brp, bci, bval);
-        rhs_mode = choose_rhs(p, (int64_t)bci.size());
+        rhs_mode = choose_rhs(p, p.nnz_m(), (int64_t)bci.size());
+        if (rhs_mode == kRhsMPass) materialise_m(p);
         if (rhs_mode == kRhsStage) {
             std::unique_ptr<Plan> sub(new Plan());
             sub->is_sub = true;
@@ -140,7 +151,7 @@ void pack(Plan &p) {
             nnz_rhs = sub->nnz_streamed;
             p.sub = std::move(sub);
         } else {
-            nnz_rhs = (int64_t)p.m_col.size();
+            nnz_rhs = p.nnz_m();
         }
     }
     std::vector<int64_t> len((size_t)n);

@@ -164,6 +164,10 @@ struct Plan {
     std::vector<int64_t> lp_ptr, m_ptr;  // L' and M in CSR
     std::vector<int32_t> lp_col, m_col;
     std::vector<double> lp_val, m_val;
+    // M's entries are held (m_col, m_val) unless the stage solve replaces
+    // the M pass; m_ptr always holds its row counts
+    bool m_kept = true;
+    int64_t nnz_m() const { return m_ptr.empty() ? 0 : m_ptr.back(); }
     std::vector<int32_t> level_rw;  // levels of L'
     int32_t nlev_rw = 0;
     std::vector<int32_t> sched_ptr, sched_rows;
@@ -214,9 +218,15 @@ void level_sets(int32_t n, const int32_t *level, int32_t nlev, std::vector<int32
 // rewrite.cpp
 void validate_policy(const sptrsv_policy &pol);
 void rewrite(Plan &p, const sptrsv_policy &pol);
+// M's entries of a plan whose rewrite did not store them (same values)
+void materialise_m(Plan &p);
 
 // pack.cpp
 void pack(Plan &p);
+// entries of L_B (entries of L whose two rows' levels share a stage)
+int64_t stage_system_nnz(const Plan &p);
+// right-hand-side step for nnz_m entries of M and nnz_b of L_B
+int32_t choose_rhs(const Plan &p, int64_t nnz_m, int64_t nnz_b);
 
 }  // namespace sptrsv
 

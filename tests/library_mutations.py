@@ -38,6 +38,14 @@ MUTANTS = [
     ("rewrite.cpp", "depth rule <= for <", r"width <= pol\.max_width && depth < pol\.max_depth;",
      "width <= pol.max_width && depth <= pol.max_depth;"),
     ("rewrite.cpp", "fill budget < for <=", r"take = added \+ delta <= budget", "take = added + delta < budget"),
+    ("rewrite.cpp", "bit-set union drops a word of a dependency's set",
+     r"for \(int32_t t = 0; t < sp\.uwords\[\(size_t\)u\]; \+\+t\) B\[t\] \|= S\[t\];",
+     "for (int32_t t = 1; t < sp.uwords[(size_t)u]; ++t) B[t] |= S[t];"),
+    ("rewrite.cpp", "closed stage not renumbered by row id",
+     r"const int32_t r = rank\[\(size_t\)\(w \* 64 \+ __builtin_ctzll\(m\)\)\];",
+     "const int32_t r = w * 64 + __builtin_ctzll(m);"),
+    ("rewrite.cpp", "M's entries kept for the stage solve", r"const bool keep_m = p\.is_sub \|\| nm == 0 \|\| ",
+     "const bool keep_m = true || "),
     ("pack.cpp", "8-chunk instance threshold", r"longer \+= T\.nch > 4 \? 1 : -1;", "longer += T.nch > 8 ? 1 : -1;"),
     ("pack.cpp", "one-level stages as segments", r"ok && depth >= 2 &&", "ok && depth >= 1 &&"),
     ("capi.cpp", "bytes of the M pass", r"o->bytes_rw \+= 2 \* vb \* \(int64_t\)p\.n;", "o->bytes_rw += vb * (int64_t)p.n;"),

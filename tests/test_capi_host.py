@@ -53,7 +53,14 @@ def compare_with_oracle(sp, s, pol):
     assert np.array_equal(sol, o["stage_of_level"])
     assert np.array_equal(dol, o["delta_of_level"])
     assert info["stages"] == o["nstages"]
+    # M's entries are held only when the M pass reads them; export builds
+    # them (same values) without touching the device image
+    assert info["m_stored"] == (0 if info["rhs_mode"] == 2 else 1), info
     lp, m = plan.export()
+    after = plan.info()
+    assert after["m_stored"] == 1
+    assert (after["rhs_mode"], after["nnz_rhs"], after["device_bytes"], after["stages"]) == \
+        (info["rhs_mode"], info["nnz_rhs"], info["device_bytes"], info["stages"])
     for a, b in zip(lp, o["lp"]):
         assert np.array_equal(a, b)
     for a, b in zip(m, o["m"]):
@@ -125,6 +132,45 @@ def test_bench_policies_bit_exact(sp, name, make, cands):
         plan, o = compare_with_oracle(sp, s, _bench_policy(cand))
         assert o["nlev_rw"] < o["nlev"] or cand == "plain", (name, cand)
         plan.close()
+
+
+def _plan_arrays(plan):
+    sol, dol = plan.stages()
+    lp, m = plan.export()
+    ptr, rows = plan.schedule()
+    return [sol, dol, *lp, *m, plan.levels(1), ptr, rows]
+
+
+@pytest.mark.parametrize("make,cand", [
+    (lambda: wl.banded(10000, 200, 8, 24, seed=2), "depth512"),
+    (lambda: wl.banded(20000, 200, 8, 24, seed=4), "depth64"),
+    (lambda: wl.powerlaw(20000, 2000, seed=3), "depth256"),
+    (lambda: wl.powerlaw(200000, 20000, seed=3), "paper256"),
+    (lambda: wl.stencil3d(24, seed=1), "depth16"),
+    (lambda: wl.random_lower(400, 0.03, seed=7), "depth64"),
+], ids=["banded-512", "banded-64", "powerlaw-256", "powerlaw-paper256", "3d-16", "random-64"])
+def test_stage_representations_agree(sp, monkeypatch, make, cand):
+    """A stage's rewritten rows are built from bit sets over the stage's
+    local index space while it is small, else from sorted lists, and a stage
+    that outgrows the limit switches from one to the other; every limit
+    (0: lists only; 64 and 300: switches inside stages) gives the same plan
+    bit for bit, and the default one matches the oracle."""
+    s = make()
+    pol = _bench_policy(cand)
+    kw = {k: v for k, v in pol.items() if k != "kind"}
+    ref = None
+    for bits in ("0", "64", "300", ""):
+        monkeypatch.setenv("SPTRSV_DENSE_STAGE_BITS", bits)
+        plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite(pol["kind"], **kw)
+        arrays = _plan_arrays(plan)
+        plan.close()
+        if ref is None:
+            ref = arrays
+            continue
+        for a, b in zip(arrays, ref):
+            assert np.array_equal(a, b), bits
+    monkeypatch.delenv("SPTRSV_DENSE_STAGE_BITS")
+    compare_with_oracle(sp, s, pol)[0].close()
 
 
 def test_explicit_masks_bit_exact(sp):
@@ -475,7 +521,17 @@ def test_rhs_modes(sp):
     here from the stage of every level); the rewrite itself is unchanged."""
     s = wl.banded(4000, 200, 8, 24, seed=9)
     plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", max_width=INF, max_depth=16, max_fill=12.0)
+    # the stage solve does not read M: only its row counts are kept ...
+    assert plan.info()["m_stored"] == 0 and plan.info()["nnz_m"] > 0
+    # ... and the M pass builds its entries (compared below with export's)
+    plan.set_rhs_mode("mpass")
+    assert plan.info()["m_stored"] == 1 and plan.info()["rhs_mode"] == 1
+    lp_mp, m_mp = plan.export()
+    plan.set_rhs_mode("auto").rewrite("threshold", max_width=INF, max_depth=16, max_fill=12.0)
+    assert plan.info()["m_stored"] == 0
     lp0, m0 = plan.export()
+    for a, b in zip(lp_mp + m_mp, lp0 + m0):
+        assert np.array_equal(a, b)
     sol, _ = plan.stages()
     lev = plan.levels(0)
     st = sol[lev]
