@@ -196,15 +196,19 @@ def test_learned_plan_is_the_oracle_plan(torch, sp, model, make):
 
 
 def test_learned_gain_on_heldout(torch, sp, model):
-    """Held-out matrices (seeds never trained on): the judged plan is never
-    slower than the threshold heuristic's (up to timing noise), and the
-    learned plans are faster than the heuristic's in geometric mean."""
+    """Held-out matrices (seeds never trained on): re-timed on fresh samples
+    after the choice, the judged plan is not slower than the threshold
+    heuristic's beyond timing noise (10%) on any matrix and not slower in
+    geometric mean, and the learned plans are faster than the heuristic's in
+    geometric mean."""
     from paper_2103_11445_amd.learn import HELDOUT_SEED, evaluate
     params = model[0].cpu().numpy()
     seeds = [HELDOUT_SEED + 100 + m for m in range(8)]
     summary, rows = evaluate(torch, params, seeds, reps=5, nmax=2e5)
     print(summary, flush=True)
     for r in rows:
-        print(r["matrix"], r["threshold_ms"], r["learned_ms"], r["chosen"], flush=True)
-        assert r["judged_ms"] <= r["threshold_ms"] * 1.0001
+        print(r["matrix"], r["threshold_ms"], r["learned_ms"], r["chosen"], r["judged_ms"],
+              r["threshold_fresh_ms"], flush=True)
+        assert r["judged_ms"] <= r["threshold_fresh_ms"] * 1.10
+    assert summary["geomean_speedup_judged_vs_threshold"] >= 1.0
     assert summary["geomean_speedup_learned_vs_threshold"] > 1.0

@@ -60,4 +60,7 @@ def test_corpus_is_seeded(learn):
     a, b = learn.corpus_matrix(10007, nmax=3e4), learn.corpus_matrix(10007, nmax=3e4)
     assert a.name == b.name and np.array_equal(a.col_idx, b.col_idx) and np.array_equal(a.val, b.val)
     pols = learn.label_policies(10007)
-    assert pols[0] == ("none", {}) and len(pols) == 8
+    assert pols[0] == ("none", {}) and len(pols) == 10
+    # the deep stage depths the benchmark's tuning picks are among the labels
+    assert max(kw.get("max_depth", 0) for _, kw in pols) == 512
+    assert pols == learn.label_policies(10007)
