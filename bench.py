@@ -59,7 +59,7 @@ CANDIDATES = {
     "depth256": ("threshold", {"max_width": INF, "max_depth": 256, "max_fill": 72.0}),
     # tried only when the next shallower one wins (see DEEPER): the host-side
     # rewrite grows with the stage depth (the banded matrix at 512 levels:
-    # ~30 s and ~25 GB of host memory for M)
+    # ~10 s and ~9 GB of host memory)
     "depth512": ("threshold", {"max_width": INF, "max_depth": 512, "max_fill": 140.0}),
 }
 DEEPER = {"depth256": "depth512"}
@@ -69,9 +69,37 @@ TUNED = {"stencil3d_128": "depth4", "banded_1m": "depth512", "powerlaw_4m": "pap
 TUNED_TILING = {"stencil3d_128": 4, "banded_1m": 8, "powerlaw_4m": 2, "stencil2d_100": 4}
 TUNED_WAVES = {"stencil3d_128": 0, "banded_1m": 0, "powerlaw_4m": 0, "stencil2d_100": 0}
 # share of the waves (per mille) serving the chain queue (0 = the library's choice)
-TUNED_CHAIN = {"stencil3d_128": 0, "banded_1m": 375, "powerlaw_4m": 0, "stencil2d_100": 0}
+TUNED_CHAIN = {"stencil3d_128": 0, "banded_1m": 250, "powerlaw_4m": 0, "stencil2d_100": 0}
 # work queues of the device schedule (2: chain and sinks apart, 1: one queue)
 TUNED_QUEUES = {"stencil3d_128": 2, "banded_1m": 2, "powerlaw_4m": 1, "stencil2d_100": 2}
+# Rewrite policies of the batched workload's union: its budget of added
+# entries is a multiple of the union's entries (every right-hand side's copy
+# counted)
+BATCH_CANDIDATES = {
+    "plain": ("none", {}),
+    "depth4": ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 4.0}),
+    "depth16": ("threshold", {"max_width": INF, "max_depth": 16, "max_fill": 4.0}),
+    "depth64": ("threshold", {"max_width": INF, "max_depth": 64, "max_fill": 4.0}),
+}
+
+
+def prec_candidates_for(k: int) -> dict:
+    """Rewrite policies of the precision workload (the union of k copies of
+    one system: its thin levels are k times wider)."""
+    return {
+        "paper64": ("threshold", {"max_width": 4 * k, "max_depth": 64, "max_fill": 0.25}),
+        "paper256": ("threshold", {"max_width": 4 * k, "max_depth": 256, "max_fill": 1.0}),
+        "depth2": ("threshold", {"max_width": INF, "max_depth": 2, "max_fill": 12.0}),
+        "depth4": ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 12.0}),
+    }
+
+
+# Recorded autotuner choices of the batched workload (rewrite of the union,
+# terms per lane, waves per CU, queues, chain share) and of its plain-union
+# comparator, and of the precision workload's rewrite (terms per lane, queues)
+TUNED_BATCH = {"policy": "depth4", "tiling": 8, "waves": 2, "queues": 2, "chain": 0}
+TUNED_BATCH_PLAIN = {"tiling": 4, "waves": 2, "queues": 1, "chain": 0}
+TUNED_PREC = {"policy": "paper64", "tiling": 8, "queues": 2}
 CHAIN_CANDIDATES = (125, 250, 375, 500, 625, 750, 875)
 
 
@@ -215,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU legs (and the parity check)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="large workload: skip the batched and precision summaries (recorded tuning)")
     ap.add_argument("--flush-mb", type=int, default=0, metavar="MB",
                     help="counter runs only: copy MB of device memory before every solve of the timed "
                          "leg (evicts the 256 MB Infinity Cache); no throughput is reported")
@@ -348,28 +378,45 @@ def main():
             if not queue and best[2] in DEEPER and DEEPER[best[2]] not in tuning[n]:
                 queue.append(DEEPER[best[2]])
         _, plans[n], chosen[n], h = best
-        host[n].update(h)
-        # row-to-wavefront tiling of the chosen plan: the recorded tuning (for
-        # the recorded policy, else 4 terms per lane) is kept unless another
-        # tiling is faster by more than 3%
-        def retile(tpl):
-            p = plans[n].set_tiling(tpl)
+        # finalists (the policies within 5% of the fastest, at most two) go
+        # through the sweep of row-to-wavefront tiling x work queues, since
+        # the two interact; the recorded choice (for the recorded policy, else
+        # 4 terms per lane and two queues) is kept unless another point is
+        # faster by more than 3%
+        screened = sorted((v["ms"], c) for c, v in tuning[n].items() if v["status"] == 0)
+        finalists = [c for ms_, c in screened if ms_ <= 1.05 * screened[0][0]][:2]
+        cand_plans = {chosen[n]: (plans[n], h)}
+
+        def retile(p, cand, tpl, q):
+            p.set_tiling(tpl).set_queues(q)
             p._buf = None
             p.upload()
             ms = time_solves(p, n, 2)
-            tuning[n][f"{chosen[n]}/t{tpl}"] = {"ms": ms, "levels_rw": p.info()["levels_rw"],
-                                               "entries": tuning[n][chosen[n]]["entries"], "status": p.check()}
-            log(f"[tune] {n} {chosen[n]} terms/lane {tpl}: {ms:.3f} ms")
+            tuning[n][f"{cand}/t{tpl}/q{q}"] = {"ms": ms, "levels_rw": p.info()["levels_rw"],
+                                                "entries": tuning[n][cand]["entries"], "status": p.check()}
+            log(f"[tune] {n} {cand} terms/lane {tpl} queues {q}: {ms:.3f} ms")
             return ms
-        tiling[n] = TUNED_TILING.get(n, 4) if chosen[n] == TUNED.get(n) else 4
-        best_ms = best[0] if tiling[n] == 4 else retile(tiling[n])
-        for tpl in (2, 4, 8, 16):
-            if tpl == tiling[n]:
-                continue
-            ms = retile(tpl)
-            if ms < 0.97 * best_ms:
-                best_ms, tiling[n] = ms, tpl
-        plans[n].set_tiling(tiling[n])
+        best_cfg = None
+        for cand in finalists:
+            if cand not in cand_plans:
+                cand_plans[cand] = make_plan(n, cand)
+            p = cand_plans[cand][0]
+            rec = (TUNED_TILING.get(n, 4), TUNED_QUEUES.get(n, 2)) if cand == TUNED.get(n) else (4, 2)
+            local = None
+            for tpl, q in [rec] + [(t, q) for q in (2, 1) for t in (2, 4, 8, 16) if (t, q) != rec]:
+                ms = retile(p, cand, tpl, q)
+                if local is None or ms < 0.97 * local[0]:
+                    local = (ms, tpl, q)
+            if best_cfg is None or local[0] < best_cfg[0]:
+                best_cfg = (local[0], cand, local[1], local[2])
+        for cand, (p, _) in cand_plans.items():
+            if cand != best_cfg[1]:
+                p.close()
+        chosen[n] = best_cfg[1]
+        plans[n], h = cand_plans[chosen[n]]
+        host[n].update(h)
+        tiling[n], queues[n] = best_cfg[2], best_cfg[3]
+        plans[n].set_tiling(tiling[n]).set_queues(queues[n])
         plans[n]._buf = None
         plans[n].upload()
         # waves per CU of the cooperative launch (0 = chosen from the plan)
@@ -388,7 +435,7 @@ def main():
         # share of the waves serving the chain queue (plans with both queues)
         chain[n] = 0
         i = plans[n].info()
-        if 0 < i["chain_items"] < i["tiles"]:
+        if queues[n] == 2 and 0 < i["chain_items"] < i["tiles"]:
             for cw in CHAIN_CANDIDATES:
                 plans[n].set_chain_share(cw)
                 ms = time_solves(plans[n], n, 2)
@@ -399,23 +446,6 @@ def main():
                 if ms < 0.97 * best_ms:
                     best_ms, chain[n] = ms, cw
         plans[n].set_chain_share(chain[n])
-        # one queue of every row in level order instead
-        queues[n] = 2
-        if 0 < i["chain_items"] < i["tiles"]:
-            plans[n].set_queues(1)
-            plans[n]._buf = None
-            plans[n].upload()
-            ms = time_solves(plans[n], n, 2)
-            tuning[n][f"{chosen[n]}/t{tiling[n]}/wpc{waves[n]}/one-queue"] = {
-                "ms": ms, "levels_rw": i["levels_rw"], "entries": tuning[n][chosen[n]]["entries"],
-                "status": plans[n].check()}
-            log(f"[tune] {n} {chosen[n]} one queue: {ms:.3f} ms")
-            if ms < 0.97 * best_ms:
-                best_ms, queues[n] = ms, 1
-            else:
-                plans[n].set_queues(2)
-                plans[n]._buf = None
-                plans[n].upload()
 
     if args.flush_mb:
         # counter runs: every solve starts with the Infinity Cache evicted
@@ -582,12 +612,30 @@ def main():
         p.close()
     del bs, xs
     torch.cuda.synchronize()
+    if args.workload == "large" and not args.no_extras:
+        # the batched (many systems and right-hand sides in one launch) and
+        # precision (FP32 storage refined in FP64) workloads with their
+        # recorded tuning, summarised in the same line
+        ns = argparse.Namespace(**{**vars(args), "no_tune": True, "no_plain": True, "steps": 10,
+                                   "warmup": 2, "plain_steps": 1})
+        bat = bench_batched(ns, torch, sp, workloads, stream, emit=False)
+        out["batched"] = {k: bat[k] for k in ("value", "unit", "ms_per_step", "speedup_vs_plain_union",
+                                               "plain_union_ms", "parity_ok", "max_rel_err_floored")}
+        out["batched"].update(config=bat["config"], roofline_frac=bat["roofline"]["frac"])
+        pre = bench_precision(ns, torch, sp, workloads, stream, emit=False)
+        out["precision"] = {k: pre[k] for k in ("value", "unit", "ms_per_step", "speedup_vs_plain_fp64",
+                                                 "speedup_vs_rewritten_fp64", "fp32_solve_over_fp64_solve",
+                                                 "parity_ok")}
+        out["precision"].update(config=pre["config"], refined=pre["legs"]["fp32_refined"],
+                                fp64_rewritten_ms=pre["legs"]["fp64_rewritten"]["ms"])
+        parity = parity is not False and bat["parity_ok"] is not False and pre["parity_ok"] is not False \
+            if parity is not None else parity
     print(json.dumps(out), flush=True)
     if parity is False:
         sys.exit(1)
 
 
-def bench_batched(args, torch, sp, workloads, stream):
+def bench_batched(args, torch, sp, workloads, stream, emit=True):
     """64 systems of uneven size (n log-uniform in [1e3, 2e5], four families)
     with 1, 4, 8 or 32 right-hand sides each, solved by one graph-captured
     launch of one batched plan (the copies of a row for several right-hand
@@ -642,14 +690,7 @@ def bench_batched(args, torch, sp, workloads, stream):
         log(f"[tune] {tag}: {ms:.3f} ms")
         return ms
 
-    # rewrite policies for the union: its budget of added entries is a
-    # multiple of the union's entries (every right-hand side's copy counted)
-    batch_candidates = {
-        "plain": ("none", {}),
-        "depth4": ("threshold", {"max_width": INF, "max_depth": 4, "max_fill": 4.0}),
-        "depth16": ("threshold", {"max_width": INF, "max_depth": 16, "max_fill": 4.0}),
-        "depth64": ("threshold", {"max_width": INF, "max_depth": 64, "max_fill": 4.0}),
-    }
+    batch_candidates = BATCH_CANDIDATES
     current = [None]
 
     def setup(cand, tpl=4, queues=2):
@@ -695,15 +736,25 @@ def bench_batched(args, torch, sp, workloads, stream):
                 best = (ms, best[1], best[2], 1, 0)
         return best
 
-    screen = {}
-    for cand in batch_candidates:
-        t_rw = setup(cand)
-        screen[cand] = measure(f"{cand}/screen")
-        log(f"[tune] {cand} rewrite {t_rw:.1f} s")
-    best_cand = min((c for c in screen if c != "plain"), key=lambda c: screen[c])
-    plain_best = tune("plain")
-    ms, tpl, wpc, queues, share = tune(best_cand)
-    cand = best_cand
+    if args.no_tune:
+        # the recorded choices: the plain union measured once at its own
+        P = TUNED_BATCH_PLAIN
+        setup("plain", P["tiling"], P["queues"])
+        plan.set_launch(P["waves"]).set_chain_share(P["chain"])
+        plain_best = (measure("plain/recorded", max(args.plain_steps, 2)), P["tiling"], P["waves"],
+                      P["queues"], P["chain"])
+        R = TUNED_BATCH
+        cand, tpl, wpc, queues, share = R["policy"], R["tiling"], R["waves"], R["queues"], R["chain"]
+    else:
+        screen = {}
+        for cand in batch_candidates:
+            t_rw = setup(cand)
+            screen[cand] = measure(f"{cand}/screen")
+            log(f"[tune] {cand} rewrite {t_rw:.1f} s")
+        best_cand = min((c for c in screen if c != "plain"), key=lambda c: screen[c])
+        plain_best = tune("plain")
+        ms, tpl, wpc, queues, share = tune(best_cand)
+        cand = best_cand
     setup(cand, tpl, queues)
     plan.set_launch(wpc).set_chain_share(share)
     for _ in range(args.warmup):
@@ -768,12 +819,14 @@ def bench_batched(args, torch, sp, workloads, stream):
     for p_, _, _ in (plains if not args.no_plain else []):
         p_.close()
     torch.cuda.synchronize()
+    if not emit:
+        return out
     print(json.dumps(out), flush=True)
     if out["parity_ok"] is False:
         sys.exit(1)
 
 
-def bench_precision(args, torch, sp, workloads, stream):
+def bench_precision(args, torch, sp, workloads, stream, emit=True):
     """The power-law matrix (n=4e6) with its values rounded to FP32 -- that
     FP32-valued matrix is the problem -- and 8 right-hand sides, as one
     batched plan of 8 copies.  Timed: FP32 solves refined by FP64 residuals
@@ -826,13 +879,46 @@ def bench_precision(args, torch, sp, workloads, stream):
     plain_ms = timed(lambda: plan.solve(b, x), max(args.plain_steps, 1))
     res["fp64_plain"] = {"ms": plain_ms, "status": plan.check(), "error": errs(x), "levels": plan.info()["levels_rw"]}
     log(f"[precision] FP64 plain: {res['fp64_plain']}")
-    # the large workload's tuned power-law plan (thin levels of one system
-    # are k times wider in the union of k copies)
-    kind, kw = CANDIDATES[TUNED["powerlaw_4m"]]
-    kw = {**kw, "max_width": kw["max_width"] * k}
-    t0 = time.perf_counter()
-    plan.rewrite(kind, **kw).set_tiling(TUNED_TILING["powerlaw_4m"]).set_queues(TUNED_QUEUES["powerlaw_4m"])
-    t_rw = time.perf_counter() - t0
+    # the rewrite of the union of k copies, tuned on the FP64 solve (thin
+    # levels of one system are k times wider in the union); the FP32 legs
+    # then use the same plan
+    prec_candidates = prec_candidates_for(k)
+    tuning = {}
+    best = None
+    for cand, (kind_, kw_) in prec_candidates.items():
+        if args.no_tune:
+            break
+        t0 = time.perf_counter()
+        plan.rewrite(kind_, **kw_)
+        t_rw_ = time.perf_counter() - t0
+        plan._buf = None
+        plan.upload()
+        ms_ = timed(lambda: plan.solve(b, x), 3)
+        tuning[cand] = round(ms_, 4)
+        log(f"[precision] tune {cand}: {ms_:.3f} ms (rewrite {t_rw_:.1f} s)")
+        if best is None or ms_ < best[0]:
+            best = (ms_, cand, 4, 2, t_rw_)
+    if args.no_tune:
+        cand = TUNED_PREC["policy"]
+        t0 = time.perf_counter()
+        kind_, kw_ = prec_candidates[cand]
+        plan.rewrite(kind_, **kw_)
+        best = (None, cand, TUNED_PREC["tiling"], TUNED_PREC["queues"], time.perf_counter() - t0)
+    cand = best[1]
+    kind, kw = prec_candidates[cand]
+    if not args.no_tune:
+        plan.rewrite(kind, **kw)
+    t_rw = best[4]
+    for tpl, q in (() if args.no_tune else ((2, 2), (8, 2), (4, 1))):
+        plan.set_tiling(tpl).set_queues(q)
+        plan._buf = None
+        plan.upload()
+        ms_ = timed(lambda: plan.solve(b, x), 3)
+        tuning[f"{cand}/t{tpl}/q{q}"] = round(ms_, 4)
+        log(f"[precision] tune {cand} terms/lane {tpl} queues {q}: {ms_:.3f} ms")
+        if ms_ < best[0]:
+            best = (ms_, cand, tpl, q, t_rw)
+    plan.set_tiling(best[2]).set_queues(best[3])
     plan._buf = None
     plan.upload()
     ms64 = timed(lambda: plan.solve(b, x), args.steps)
@@ -869,8 +955,9 @@ def bench_precision(args, torch, sp, workloads, stream):
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "power-law n=4e6 (Zipf 1.8 rows capped at 64, 20k-row serial tail) with "
                                "FP32-rounded values, 8 right-hand sides, FP32 solves refined in FP64",
-                   "rhs_per_step": k, "union_rows": info["n"], "policy": {"kind": kind, **kw},
-                   "rewrite_s": t_rw},
+                   "rhs_per_step": k, "union_rows": info["n"], "policy": {"name": cand, "kind": kind, **kw},
+                   "terms_per_lane": best[2], "queues": best[3], "rewrite_s": t_rw},
+        "tuning_ms": tuning,
         "roofline": {"bound": "hbm", "achieved": call_bytes / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": call_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None},
@@ -886,6 +973,8 @@ def bench_precision(args, torch, sp, workloads, stream):
     }
     plan.close()
     torch.cuda.synchronize()
+    if not emit:
+        return out
     print(json.dumps(out), flush=True)
     if out["parity_ok"] is False:
         sys.exit(1)

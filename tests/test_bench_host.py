@@ -31,6 +31,14 @@ def test_recorded_tuning_is_buildable():
         assert b.TUNED_WAVES[name] in (0, 2, 4, 8)
         assert b.TUNED_CHAIN[name] in (0,) + b.CHAIN_CANDIDATES
         assert b.TUNED_QUEUES[name] in (1, 2)
+    # the batched and precision workloads' recorded choices (used by the
+    # default run's summaries of those workloads)
+    assert b.TUNED_BATCH["policy"] in b.BATCH_CANDIDATES
+    for t in (b.TUNED_BATCH, b.TUNED_BATCH_PLAIN):
+        assert t["tiling"] in (2, 4, 8, 16) and t["waves"] in (0, 2, 4, 8)
+        assert t["queues"] in (1, 2) and t["chain"] in (0, 250, 500, 750)
+    assert b.TUNED_PREC["policy"] in b.prec_candidates_for(8)
+    assert b.TUNED_PREC["tiling"] in (2, 4, 8) and b.TUNED_PREC["queues"] in (1, 2)
     for shallow, deep in b.DEEPER.items():
         assert shallow in b.CANDIDATES and deep in b.CANDIDATES
         assert b.CANDIDATES[deep][1]["max_depth"] > b.CANDIDATES[shallow][1]["max_depth"]
