@@ -411,8 +411,10 @@ __device__ inline void load_tile(const SolveArgs<V> &a, const int4 d, int lane, 
 #pragma unroll
     for (int c = 0; c < kReg; ++c) {
         const bool ok = active && c < d.z;
-        T.col[c] = *(ok ? a.tcol + base + (size_t)c * 64 : a.rows);
-        T.val[c] = *(ok ? a.tval + base + (size_t)c * 64 : a.diag);
+        // terms are read once per solve: streaming loads, so that they do
+        // not evict the lines of x that the dependency chain reads back
+        T.col[c] = __builtin_nontemporal_load(ok ? a.tcol + base + (size_t)c * 64 : a.rows);
+        T.val[c] = __builtin_nontemporal_load(ok ? a.tval + base + (size_t)c * 64 : a.diag);
     }
     const int32_t slot = tile_lead(d, lane) ? d.y + (lane >> tile_lg(d)) : 0;
     T.row = a.rows[slot];
@@ -628,8 +630,8 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
 #pragma unroll
             for (int u = 0; u < kReg; ++u) {
                 const size_t idx = base + (size_t)(c0 + u < cur.d.z ? c0 + u : c0) * 64;
-                kc[u] = a.tcol[idx];
-                vc[u] = a.tval[idx];
+                kc[u] = __builtin_nontemporal_load(a.tcol + idx);
+                vc[u] = __builtin_nontemporal_load(a.tval + idx);
             }
 #pragma unroll
             for (int u = 0; u < kReg; ++u) {
