@@ -375,8 +375,12 @@ def main():
                 best = (ms, p, cand, h)
             else:
                 p.close()
-            if not queue and best[2] in DEEPER and DEEPER[best[2]] not in tuning[n]:
-                queue.append(DEEPER[best[2]])
+            if not queue:
+                # the next depth when the best fixed policy is the deepest one tried
+                fixed = [(v["ms"], c) for c, v in tuning[n].items() if c in CANDIDATES and v["status"] == 0]
+                top = min(fixed)[1] if fixed else None
+                if top in DEEPER and DEEPER[top] not in tuning[n]:
+                    queue.append(DEEPER[top])
         _, plans[n], chosen[n], h = best
         # finalists (the policies within 5% of the fastest, at most two) go
         # through the sweep of row-to-wavefront tiling x work queues, since
@@ -407,8 +411,12 @@ def main():
                 ms = retile(p, cand, tpl, q)
                 if local is None or ms < 0.97 * local[0]:
                     local = (ms, tpl, q)
-            if best_cfg is None or local[0] < best_cfg[0]:
-                best_cfg = (local[0], cand, local[1], local[2])
+            # the learned policy is kept over a fixed one only when it is
+            # faster by more than 3% (it often reproduces a fixed depth's
+            # stages, and then the recorded name is kept)
+            score = local[0] * (1.03 if cand == "learned" else 1.0)
+            if best_cfg is None or score < best_cfg[4]:
+                best_cfg = (local[0], cand, local[1], local[2], score)
         for cand, (p, _) in cand_plans.items():
             if cand != best_cfg[1]:
                 p.close()
