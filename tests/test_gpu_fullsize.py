@@ -1,7 +1,8 @@
 """GPU parity at the benchmark's full sizes and launch configuration: the
 three large systems (3D stencil 128^3, banded n=1e6, power-law n=4e6) with the
-tuned policies and tilings bench.py times, every component against the FP64
-oracle (floored componentwise error <= 1e-10), plus the plain schedule."""
+recorded policies, tilings, queues, waves and chain shares bench.py times,
+every component against the FP64 oracle (floored componentwise error <= 1e-10,
+and <= 1e-12, the rounding-level sentinel), plus the plain schedule."""
 import importlib.util
 import os
 
@@ -10,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gate import TOL, errors, report
+from gate import SENTINEL, TOL, errors, report
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -49,8 +50,11 @@ def test_large_tuned(torch, sp, bench, name):
     for label, policy in (("tuned", (kind, kw)), ("plain", ("none", {}))):
         plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite(policy[0], **policy[1])
         if label == "tuned":
-            plan.set_tiling(bench.TUNED_TILING[name])
+            # the launch configuration the benchmark times
+            plan.set_tiling(bench.TUNED_TILING[name]).set_queues(bench.TUNED_QUEUES[name])
         plan.upload()
+        if label == "tuned":
+            plan.set_launch(bench.TUNED_WAVES[name]).set_chain_share(bench.TUNED_CHAIN[name])
         x = plan.solve(b)
         assert plan.check() == 0
         err = errors(x.cpu().numpy(), ref)
@@ -58,5 +62,6 @@ def test_large_tuned(torch, sp, bench, name):
         print(name, label, info["levels_rw"], info["rhs_mode"], report(x.cpu().numpy(), ref), flush=True)
         assert np.all(np.isfinite(x.cpu().numpy()))
         assert err[1] <= TOL
+        assert err[1] <= SENTINEL, err
         plan.close()
         del x
