@@ -359,6 +359,13 @@ def main(argv=None):
     t.add_argument("--rhs-share", action="store_true",
                    help="charge each level its share of the right-hand-side step in the labels")
     t.add_argument("--report", default=None, help="JSON file for the evaluation")
+    t.add_argument("--first", type=int, default=0, help="first training matrix to collect labels for")
+    t.add_argument("--labels-out", default=None,
+                   help="save the collected labels (npz) to continue in another process")
+    t.add_argument("--labels-in", nargs="*", default=[],
+                   help="labels saved by earlier runs (npz), trained on with the new ones")
+    t.add_argument("--max-samples", type=int, default=0,
+                   help="keep a seeded random subset of at most this many of the new samples (0: all)")
     e = sub.add_parser("evaluate")
     e.add_argument("--model", default=DEFAULT_MODEL)
     e.add_argument("--heldout", type=int, default=40)
@@ -371,21 +378,48 @@ def main(argv=None):
     load()
     if args.cmd == "train":
         t0 = time.perf_counter()
-        X, y, used = collect(torch, [TRAIN_SEED + m for m in range(args.train)], budget_s=args.budget,
-                             with_rhs=args.rhs_share)
-        t_collect = time.perf_counter() - t0
-        log(f"[collect] {X.shape[0]} samples from {used} matrices in {t_collect:.0f} s")
-        params, hist = train(torch, X, y, steps=args.steps)
-        meta = {"train_matrices": used, "train_seed": TRAIN_SEED, "samples": int(X.shape[0]),
-                "n_range": [1e4, 1e6], "rhs_share": bool(args.rhs_share),
-                "steps": args.steps, "loss": hist, "label": "ln(level time in microseconds)",
-                "collect_s": t_collect}
-        save_model(args.out, params, meta)
-        log(f"[train] saved {args.out}")
-        params_eval = params
+        Xs, ys, ranges, t_collect = [], [], [], 0.0
+        for path in args.labels_in:
+            with np.load(path, allow_pickle=False) as z:
+                Xs.append(z["X"])
+                ys.append(z["y"])
+                ranges.append([int(z["first"]), int(z["used"])])
+                t_collect += float(z["collect_s"])
+        if args.train > args.first:
+            X, y, used = collect(torch, [TRAIN_SEED + m for m in range(args.first, args.train)],
+                                 budget_s=args.budget, with_rhs=args.rhs_share)
+            dt = time.perf_counter() - t0
+            t_collect += dt
+            log(f"[collect] {X.shape[0]} samples from {used} matrices in {dt:.0f} s")
+            if 0 < args.max_samples < X.shape[0]:
+                keep = np.sort(np.random.default_rng(args.first).choice(X.shape[0], args.max_samples,
+                                                                        replace=False))
+                X, y = X[keep], y[keep]
+                log(f"[collect] kept a random {args.max_samples} of them")
+            if args.labels_out:
+                np.savez_compressed(args.labels_out, X=X.astype(np.float32), y=y.astype(np.float32),
+                                    first=args.first, used=used, collect_s=dt)
+                log(f"[collect] labels saved to {args.labels_out}")
+            Xs.append(X)
+            ys.append(y)
+            ranges.append([args.first, used])
+        X, y = np.concatenate(Xs), np.concatenate(ys)
+        # the training matrices: seeds TRAIN_SEED + [first, first + used) of each part
+        used = sum(r[1] for r in ranges)
+        if args.steps > 0:
+            params, hist = train(torch, X, y, steps=args.steps)
+            meta = {"train_matrices": used, "train_seed": TRAIN_SEED, "train_ranges": ranges,
+                    "samples": int(X.shape[0]), "n_range": [1e4, 1e6], "rhs_share": bool(args.rhs_share),
+                    "steps": args.steps, "loss": hist, "label": "ln(level time in microseconds)",
+                    "collect_s": t_collect}
+            save_model(args.out, params, meta)
+            log(f"[train] saved {args.out} ({X.shape[0]} samples, {used} matrices)")
+            params_eval = params
+        else:
+            params_eval, meta = None, None  # labels only
     else:
         params_eval, meta = load_model(args.model)
-    if args.heldout:
+    if args.heldout and params_eval is not None:
         first = args.first if args.cmd == "evaluate" else 0
         summary, rows = evaluate(torch, params_eval, [HELDOUT_SEED + m for m in range(first, args.heldout)],
                                  budget_s=args.budget if args.cmd == "evaluate" else float("inf"))
