@@ -64,3 +64,20 @@ def test_corpus_is_seeded(learn):
     # the deep stage depths the benchmark's tuning picks are among the labels
     assert max(kw.get("max_depth", 0) for _, kw in pols) == 512
     assert pols == learn.label_policies(10007)
+
+
+def test_label_parts_merge(learn, tmp_path, capsys):
+    """Labels collected in parts (each its own seed range, saved as npz) are
+    read back and trained on together; with no new matrices and no training
+    steps nothing touches the GPU."""
+    rng = np.random.default_rng(1)
+    paths = []
+    for first, used, rows in ((254, 3, 40), (257, 2, 25)):
+        X = rng.random((rows, 6)).astype(np.float32)
+        y = rng.random(rows).astype(np.float32)
+        p = tmp_path / f"labels_{first}.npz"
+        np.savez_compressed(p, X=X, y=y, first=first, used=used, collect_s=1.5)
+        paths.append(str(p))
+    learn.main(["train", "--train", "0", "--heldout", "0", "--steps", "0", "--labels-in", *paths])
+    with np.load(paths[0], allow_pickle=False) as z:
+        assert z["X"].shape == (40, 6) and int(z["used"]) == 3
