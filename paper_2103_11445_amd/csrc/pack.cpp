@@ -521,7 +521,9 @@ void pack(Plan &p) {
     }
     Ly.total = off;
 
-    p.image.assign(Ly.total, 0);
+    p.image.clear();
+    p.image.resize(Ly.total);  // left uninitialised by its allocator, then cleared in parallel
+    parallel_zero(p.image.data(), p.image.size());
     if (p.sub) std::copy(p.sub->image.begin(), p.sub->image.end(), p.image.begin() + (ptrdiff_t)Ly.sub);
     unsigned char *img = p.image.data();
     int32_t *trow = reinterpret_cast<int32_t *>(img + Ly.rows);
@@ -536,8 +538,12 @@ void pack(Plan &p) {
         else
             reinterpret_cast<double *>(img + section)[idx] = v;
     };
-    std::fill(tcol, tcol + nchunks * 64, kPad);
-    std::fill(scol, scol + nst * kSegChunks * 64, kPad);
+    parallel_ranges(nchunks * 64, hw_threads(), [&](int64_t lo, int64_t hi, int) {
+        std::fill(tcol + lo, tcol + hi, kPad);
+    });
+    parallel_ranges(nst * kSegChunks * 64, hw_threads(), [&](int64_t lo, int64_t hi, int) {
+        std::fill(scol + lo, scol + hi, kPad);
+    });
     for (int64_t q = 0; q < nst * 64; ++q) srow[4 * q] = -1;
     // the device image speaks the caller's indices (reversed for upper
     // input; a batched union is numbered like the callers' blocks already)

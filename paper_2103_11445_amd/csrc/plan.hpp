@@ -1,15 +1,87 @@
 // plan.hpp -- internal state of a plan and the host passes that build it.
 #pragma once
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <memory>
+#include <new>
 #include <string>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "sptrsv.h"
 
 namespace sptrsv {
+
+// Host worker threads for the analysis passes: the cores, at most 16.
+inline int hw_threads() {
+    unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(h, 16u));
+}
+
+// Run f(begin, end, worker) over [0, count) on up to `threads` workers.
+template <class F>
+void parallel_ranges(int64_t count, int threads, F &&f) {
+    if (count <= 0) return;
+    threads = (int)std::min<int64_t>(threads, std::max<int64_t>(1, count / 256));
+    if (threads <= 1) {
+        f((int64_t)0, count, 0);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const int64_t step = (count + threads - 1) / threads;
+    for (int w = 0; w < threads; ++w) {
+        const int64_t b = w * step, e = std::min(count, b + step);
+        if (b >= e) break;
+        pool.emplace_back([&, b, e, w] { f(b, e, w); });
+    }
+    for (auto &t : pool) t.join();
+}
+
+// Allocator whose resize leaves new elements uninitialised, so that a large
+// buffer can be cleared by several threads instead of one.
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <class U>
+    UninitAlloc(const UninitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+
+// Zero `bytes` bytes at `p` with the host's worker threads, one contiguous
+// range each (the page faults of a fresh allocation are taken in parallel).
+inline void parallel_zero(unsigned char *p, size_t bytes) {
+    constexpr size_t kBlock = size_t(1) << 20;
+    const int64_t blocks = (int64_t)((bytes + kBlock - 1) / kBlock);
+    const int threads = (int)std::min<int64_t>(hw_threads(), std::max<int64_t>(1, blocks / 4));
+    if (threads <= 1) {
+        std::memset(p, 0, bytes);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const int64_t step = (blocks + threads - 1) / threads;
+    for (int w = 0; w < threads; ++w) {
+        const size_t b = (size_t)(w * step) * kBlock;
+        if (b >= bytes) break;
+        const size_t e = std::min(bytes, (size_t)((w + 1) * step) * kBlock);
+        pool.emplace_back([p, b, e] { std::memset(p + b, 0, e - b); });
+    }
+    for (auto &t : pool) t.join();
+}
 
 // Error carried out of the host passes; the C ABI turns it into a status
 // code and a thread-local message.
@@ -174,7 +246,7 @@ struct Plan {
 
     // ---- packed device image (host copy) and its layout
     Layout layout;
-    std::vector<unsigned char> image;
+    std::vector<unsigned char, UninitAlloc<unsigned char>> image;
     int64_t ntiles = 0;      // work items (wide tiles and segments)
     int64_t nchain = 0;      // of which the chain queue (the rest hold only rows nothing depends on)
     int64_t chain_work = 0, sink_work = 0;  // 64-lane chunks plus rows packed in each queue

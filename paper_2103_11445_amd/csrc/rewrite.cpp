@@ -131,30 +131,6 @@ void row_structure(const Plan &p, const Symbolic &sym, int32_t i, int32_t a, Mar
     std::sort(bs.begin(), bs.end());
 }
 
-int hw_threads() {
-    unsigned h = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(h, 16u));
-}
-
-// Run f(begin, end, worker) over [0, count) on up to `threads` workers.
-template <class F>
-void parallel_ranges(int64_t count, int threads, F &&f) {
-    if (count <= 0) return;
-    threads = (int)std::min<int64_t>(threads, std::max<int64_t>(1, count / 256));
-    if (threads <= 1) {
-        f((int64_t)0, count, 0);
-        return;
-    }
-    std::vector<std::thread> pool;
-    const int64_t step = (count + threads - 1) / threads;
-    for (int w = 0; w < threads; ++w) {
-        const int64_t b = w * step, e = std::min(count, b + step);
-        if (b >= e) break;
-        pool.emplace_back([&, b, e, w] { f(b, e, w); });
-    }
-    for (auto &t : pool) t.join();
-}
-
 // Predicted cost (the model's output is the log of a time) of groups of
 // rows, evaluated by the model's forward kernel on the current device.
 class CostModel {
