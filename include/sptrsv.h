@@ -318,7 +318,8 @@ sptrsv_status sptrsv_set_wait_limit(sptrsv_plan plan, uint64_t ticks);
  * gathers of x and b are counted as cache hits.  bytes_rw counts the entries
  * of L' the solve reads (nnz_streamed) and those the right-hand-side step
  * reads (nnz_rhs), plus 2v per row for the M pass (b' written and read) or
- * 8 + 2v per row for the stage solve. */
+ * 8 + 2v per row for the stage solve, less 2 per term whose column a
+ * compact plan stores in 16 bits (compact_terms). */
 typedef struct {
     int32_t n;
     int32_t levels;      /* levels of L */
@@ -367,6 +368,16 @@ typedef struct {
                             and sptrsv_plan_export or a switch to the M pass
                             builds the entries then (as long as the rewrite
                             itself, same values) */
+    int32_t compact_cols;/* 1 if the wide tiles store each term's column as
+                            a 16-bit distance back from the tile's first
+                            slot (2 bytes instead of 4 per term): chosen by
+                            the packer when every distance fits and no
+                            copies share terms.  The environment variable
+                            SPTRSV_COMPACT_COLS=0, read at packing, keeps
+                            32-bit columns.  Results are the same bit for
+                            bit either way. */
+    int64_t compact_terms;/* terms stored with 16-bit columns (0 unless
+                            compact_cols) */
 } sptrsv_info;
 sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *out);
 

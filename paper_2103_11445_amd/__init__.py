@@ -63,7 +63,8 @@ class _Info(ctypes.Structure):
                 ("rhs_segments", ctypes.c_int32), ("reg_chunks", ctypes.c_int32),
                 ("segments", ctypes.c_int32), ("ring_segments", ctypes.c_int32),
                 ("chain_items", ctypes.c_int64), ("nnz_streamed", ctypes.c_int64),
-                ("m_stored", ctypes.c_int32)]
+                ("m_stored", ctypes.c_int32), ("compact_cols", ctypes.c_int32),
+                ("compact_terms", ctypes.c_int64)]
 
 
 _lib = None

@@ -515,7 +515,7 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     // the solve of L' plus the right-hand-side step: M entries and b, b' per
     // row (M pass), or a whole solve of L_B (stage solves)
     o->nnz_streamed = p.nnz_streamed;
-    o->bytes_rw = (4 + vb) * (o->nnz_streamed + o->nnz_rhs) + (8 + 2 * vb) * (int64_t)p.n;
+    o->bytes_rw = (4 + vb) * (o->nnz_streamed + o->nnz_rhs) + (8 + 2 * vb) * (int64_t)p.n - 2 * p.nnz_col16;
     if (p.layout.rhs_mode == sptrsv::kRhsMPass) o->bytes_rw += 2 * vb * (int64_t)p.n;
     if (p.layout.rhs_mode == sptrsv::kRhsStage) o->bytes_rw += (8 + 2 * vb) * (int64_t)p.n;
     o->device_bytes = (int64_t)p.layout.total;
@@ -528,6 +528,8 @@ sptrsv_status sptrsv_plan_info(sptrsv_plan plan, sptrsv_info *o) {
     o->ring_segments = p.ring_segs;
     o->chain_items = p.nchain;
     o->m_stored = p.m_kept ? 1 : 0;
+    o->compact_cols = p.layout.col16;
+    o->compact_terms = p.nnz_col16;
     return SPTRSV_OK;
 }
 

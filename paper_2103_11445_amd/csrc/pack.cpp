@@ -43,6 +43,7 @@
 // segments form the first queue of items, sink tiles the second (each in
 // level order), served by separate waves.  A sink never delays a chain row.
 #include <algorithm>
+#include <cstdlib>
 #include <climits>
 #include <cstring>
 #include <memory>
@@ -441,6 +442,42 @@ void pack(Plan &p) {
     if (mchunks > INT32_MAX || (int64_t)mtiles.size() > INT32_MAX)
         throw Error{SPTRSV_ERR_OVERFLOW, "device image needs more than INT32_MAX chunks"};
 
+    // ---- compact columns: a wide tile's terms all read earlier levels, so
+    // each column is stored as its distance back from the tile's first
+    // slot; when every distance fits in 16 bits (and no copies share terms)
+    // the column array is halved.  SPTRSV_COMPACT_COLS=0 keeps 32 bits.
+    bool compact = !tiles.empty();
+    {
+        const char *env = std::getenv("SPTRSV_COMPACT_COLS");
+        if (env && env[0] == '0') compact = false;
+    }
+    int64_t nnz_col16 = 0;
+    if (compact) {
+        const int threads = hw_threads();
+        std::vector<char> fits((size_t)threads, 1);
+        std::vector<int64_t> terms((size_t)threads, 0);
+        parallel_ranges((int64_t)tiles.size(), threads, [&](int64_t lo, int64_t hi, int w) {
+            for (int64_t t = lo; t < hi && fits[(size_t)w]; ++t) {
+                const Tile &T = tiles[(size_t)t];
+                if (T.lgk != 0 || T.c0 != 0) {
+                    fits[(size_t)w] = 0;
+                    break;
+                }
+                for (int32_t r = 0; r < T.nrows; ++r) {
+                    const int32_t i = slot_row[(size_t)(T.row_off + r)];
+                    for (int64_t q = p.lp_ptr[(size_t)i]; q < p.lp_ptr[(size_t)i + 1] - 1; ++q) {
+                        const int64_t dist = (int64_t)T.row_off - slot_of_row[(size_t)p.lp_col[(size_t)q]];
+                        if (dist < 1 || dist > 65535) fits[(size_t)w] = 0;
+                    }
+                    terms[(size_t)w] += p.lp_ptr[(size_t)i + 1] - p.lp_ptr[(size_t)i] - 1;
+                }
+            }
+        });
+        for (int w = 0; w < threads; ++w) compact = compact && fits[(size_t)w];
+        if (compact)
+            for (int64_t t : terms) nnz_col16 += t;
+    }
+
     // ---- layout
     const int64_t nst = (int64_t)stiles.size();
     const bool f32 = p.precision == 32;
@@ -465,8 +502,9 @@ void pack(Plan &p) {
     off = align256(off + (size_t)n * 4);
     Ly.diag = off;
     off = align256(off + (size_t)n * vb);
+    Ly.col16 = compact ? 1 : 0;
     Ly.tcol = off;
-    off = align256(off + (size_t)nchunks * 64 * 4);
+    off = align256(off + (size_t)nchunks * 64 * (compact ? 2 : 4));
     Ly.tval = off;
     off = align256(off + (size_t)nchunks * 64 * vb);
     Ly.scol = off;
@@ -528,6 +566,7 @@ void pack(Plan &p) {
     unsigned char *img = p.image.data();
     int32_t *trow = reinterpret_cast<int32_t *>(img + Ly.rows);
     int32_t *tcol = reinterpret_cast<int32_t *>(img + Ly.tcol);
+    uint16_t *tcol16 = reinterpret_cast<uint16_t *>(img + Ly.tcol);  // compact: 0 marks a pad
     int32_t *desc = reinterpret_cast<int32_t *>(img + Ly.tiles);
     int32_t *scol = reinterpret_cast<int32_t *>(img + Ly.scol);
     int32_t *srow = reinterpret_cast<int32_t *>(img + Ly.srow);  // {row, meta, slot, 0} per lane
@@ -538,9 +577,10 @@ void pack(Plan &p) {
         else
             reinterpret_cast<double *>(img + section)[idx] = v;
     };
-    parallel_ranges(nchunks * 64, hw_threads(), [&](int64_t lo, int64_t hi, int) {
-        std::fill(tcol + lo, tcol + hi, kPad);
-    });
+    if (!compact)
+        parallel_ranges(nchunks * 64, hw_threads(), [&](int64_t lo, int64_t hi, int) {
+            std::fill(tcol + lo, tcol + hi, kPad);
+        });
     parallel_ranges(nst * kSegChunks * 64, hw_threads(), [&](int64_t lo, int64_t hi, int) {
         std::fill(scol + lo, scol + hi, kPad);
     });
@@ -628,7 +668,10 @@ void pack(Plan &p) {
             int64_t t_ = 0;
             row_terms(i, -1, 0, [&](int32_t col, double v) {
                 const int64_t idx = (T.chunk_off + (t_ >> T.lg)) * 64 + r0 * g + (t_ & (g - 1));
-                tcol[idx] = col - c;
+                if (compact)
+                    tcol16[idx] = (uint16_t)(T.row_off - col);
+                else
+                    tcol[idx] = col - c;
                 putv(Ly.tval, idx, v);
                 ++t_;
             });
@@ -698,6 +741,7 @@ void pack(Plan &p) {
     p.ntiles = (int64_t)items.size();
     p.nchain = nchain;
     p.nnz_streamed = (p.lp_ptr.empty() ? 0 : p.lp_ptr.back()) - shared_skip;
+    p.nnz_col16 = nnz_col16;
     p.nchunks = nchunks;
     p.nseg = nseg;
     p.nseg_tiles = nst;

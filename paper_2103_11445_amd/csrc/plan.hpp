@@ -139,6 +139,7 @@ struct Layout {
     int value_bytes = 8;
     int reg_chunks = 4;  // wide-tile chunks the solve kernel holds in registers (4 or 8)
     int ring_segs = 0;   // every segment reads only its LDS ring (the lighter kernel instance)
+    int col16 = 0;       // wide-tile columns as 16-bit distances back from the tile's first slot
     int32_t rhs_mode = kRhsNone;
     size_t sub = 0;               // kRhsStage: offset of the stage system's image
     const Layout *sub_layout = nullptr;
@@ -148,7 +149,8 @@ struct Layout {
                            //   or segment {first segment tile, count, 0, 1<<31}
     size_t rows = 0;       // int32[n]      row id of each packed slot
     size_t diag = 0;       // double[n]     diagonal of each packed slot
-    size_t tcol = 0;       // int32[64*nchunks] term column: slot of the x-term's row, INT32_MIN pad
+    size_t tcol = 0;       // int32[64*nchunks] term column: slot of the x-term's row, INT32_MIN pad;
+                           //   col16: uint16[64*nchunks] first slot of the tile minus that slot, 0 pad
     size_t tval = 0;       // double[64*nchunks] term coefficient (x-terms negated)
     size_t scol = 0;       // int32[nseg_tiles][64][kSegChunks] as tcol, plus n + ring index for LDS x-terms
                            // (n + kRing, a zero slot, for the pads of a segment without gathers)
@@ -251,6 +253,7 @@ struct Plan {
     int64_t nchain = 0;      // of which the chain queue (the rest hold only rows nothing depends on)
     int64_t chain_work = 0, sink_work = 0;  // 64-lane chunks plus rows packed in each queue
     int64_t nnz_streamed = 0;  // entries of L' the image holds (copies sharing terms count once)
+    int64_t nnz_col16 = 0;     // of them, wide-tile terms whose column is stored in 16 bits
     int64_t nchunks = 0;
     int32_t nseg = 0;        // segments
     int64_t nseg_tiles = 0;  // tiles inside segments

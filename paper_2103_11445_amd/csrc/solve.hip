@@ -99,6 +99,7 @@ struct SolveArgs {
     const int32_t *rows;
     const T *diag;
     const int32_t *tcol;
+    const uint16_t *tcol16;  // the same section in the compact encoding (see tile_col)
     const T *tval;
     const int32_t *scol;
     const T *sval;
@@ -393,9 +394,17 @@ __device__ inline int tile_term_lane(const int4 d, int lane) {
 __device__ inline int32_t tile_copy(const int4 d, int lane) {
     return (((d.w >> 8) & 0xff) + (lane >> tile_lg(d))) & ((1 << tile_lgk(d)) - 1);
 }
-template <typename V, int kReg>
+// A term's column: the slot of its x.  Compact plans (kCol16) store it as
+// the distance back from the tile's first slot in 16 bits (every term reads
+// an earlier level, so the distance is at least 1; 0 marks a pad).
+template <bool kCol16>
+__device__ inline int32_t decode_col(int32_t raw, const int4 d) {
+    if (kCol16) return raw == 0 ? kPad : d.y - raw;
+    return raw;
+}
+template <bool kCol16, typename V, int kReg>
 __device__ inline int32_t tile_col(const Tile<V, kReg> &T, int c, int lane) {
-    const int32_t k = T.col[c];
+    const int32_t k = decode_col<kCol16>(T.col[c], T.d);
     return tile_active(T.d, lane) && c < T.d.z && k != kPad ? k + tile_copy(T.d, lane) : kPad;
 }
 template <typename V, int kReg>
@@ -403,7 +412,7 @@ __device__ inline V tile_val(const Tile<V, kReg> &T, int c, int lane) {
     return tile_active(T.d, lane) && c < T.d.z ? T.val[c] : V(0);
 }
 
-template <typename V, int kReg>
+template <bool kCol16, typename V, int kReg>
 __device__ inline void load_tile(const SolveArgs<V> &a, const int4 d, int lane, Tile<V, kReg> &T) {
     T.d = d;
     const bool active = tile_active(d, lane);
@@ -413,7 +422,11 @@ __device__ inline void load_tile(const SolveArgs<V> &a, const int4 d, int lane, 
         const bool ok = active && c < d.z;
         // terms are read once per solve: streaming loads, so that they do
         // not evict the lines of x that the dependency chain reads back
-        T.col[c] = __builtin_nontemporal_load(ok ? a.tcol + base + (size_t)c * 64 : a.rows);
+        if (kCol16)
+            T.col[c] = __builtin_nontemporal_load(ok ? a.tcol16 + base + (size_t)c * 64
+                                                     : reinterpret_cast<const uint16_t *>(a.rows));
+        else
+            T.col[c] = __builtin_nontemporal_load(ok ? a.tcol + base + (size_t)c * 64 : a.rows);
         T.val[c] = __builtin_nontemporal_load(ok ? a.tval + base + (size_t)c * 64 : a.diag);
     }
     const int32_t slot = tile_lead(d, lane) ? d.y + (lane >> tile_lg(d)) : 0;
@@ -562,7 +575,7 @@ __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ri
 // kRingSegs: every segment of the plan is flagged ring-only, and the
 // instance carries only that (lighter) segment loop; otherwise the general
 // loop runs every segment, ring-only ones included.
-template <typename T, bool kStamp, int kReg, bool kRingSegs>
+template <typename T, bool kStamp, int kReg, bool kRingSegs, bool kCol16>
 __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     __shared__ T ring[kRing + 1];  // x of the segment's last kRing rows, then a zero slot
     const int lane = threadIdx.x;
@@ -577,7 +590,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
     if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     int4 d = unpack_item(load_item(a, i, lane));
     Tile<T, kReg> cur;
-    if (!is_segment(d)) load_tile(a, d, lane, cur);
+    if (!is_segment(d)) load_tile<kCol16>(a, d, lane, cur);
     int wnext = load_item(a, i + stride, lane);  // raw descriptor of the next item
     for (;;) {
         const long long in = i + stride, inn = in + stride;
@@ -586,7 +599,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
             if (kStamp && lane == 0) a.stamps[i] = __builtin_amdgcn_s_memrealtime();
             if (in >= end) break;
             d = unpack_item(wnext);
-            if (!is_segment(d)) load_tile(a, d, lane, cur);
+            if (!is_segment(d)) load_tile<kCol16>(a, d, lane, cur);
             wnext = load_item(a, inn, lane);
             i = in;
             continue;
@@ -597,7 +610,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         typename Val<T>::Bits g[kReg];
 #pragma unroll
         for (int c = 0; c < kReg; ++c) {
-            col[c] = tile_col(cur, c, lane);
+            col[c] = tile_col<kCol16>(cur, c, lane);
             g[c] = gather_x(a, col[c]);
         }
         const bool lead = tile_lead(cur.d, lane);
@@ -607,7 +620,7 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
         // 2. the next tile's terms and the descriptor after it
         Tile<T, kReg> nxt;
         const bool nwide = in < end && !is_segment(dnext);
-        load_tile(a, nwide ? dnext : d, lane, nxt);
+        load_tile<kCol16>(a, nwide ? dnext : d, lane, nxt);
         const int wnn = load_item(a, inn, lane);
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
@@ -630,11 +643,15 @@ __global__ void __launch_bounds__(64) solve_tiles(SolveArgs<T> a) {
 #pragma unroll
             for (int u = 0; u < kReg; ++u) {
                 const size_t idx = base + (size_t)(c0 + u < cur.d.z ? c0 + u : c0) * 64;
-                kc[u] = __builtin_nontemporal_load(a.tcol + idx);
+                if (kCol16)
+                    kc[u] = __builtin_nontemporal_load(a.tcol16 + idx);
+                else
+                    kc[u] = __builtin_nontemporal_load(a.tcol + idx);
                 vc[u] = __builtin_nontemporal_load(a.tval + idx);
             }
 #pragma unroll
             for (int u = 0; u < kReg; ++u) {
+                kc[u] = decode_col<kCol16>(kc[u], cur.d);
                 kc[u] = !act || c0 + u >= cur.d.z || kc[u] == kPad ? kPad : kc[u] + copy;
                 gc[u] = gather_x(a, kc[u]);
             }
@@ -807,6 +824,7 @@ SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int
     a.rows = reinterpret_cast<const int32_t *>(dev + lay->rows);
     a.diag = reinterpret_cast<const T *>(dev + lay->diag);
     a.tcol = reinterpret_cast<const int32_t *>(dev + lay->tcol);
+    a.tcol16 = reinterpret_cast<const uint16_t *>(dev + lay->tcol);
     a.tval = reinterpret_cast<const T *>(dev + lay->tval);
     a.scol = reinterpret_cast<const int32_t *>(dev + lay->scol);
     a.sval = reinterpret_cast<const T *>(dev + lay->sval);
@@ -827,15 +845,19 @@ SolveArgs<T> solve_args(const unsigned char *dev, const sptrsv::Layout *lay, int
     return a;
 }
 
-template <typename T, bool kStamp>
-const void *tiles_kernel(const sptrsv::Layout *lay) {
+template <typename T, bool kStamp, bool kCol16>
+const void *tiles_kernel_of(const sptrsv::Layout *lay) {
     // the instrumented solve runs every plan with the general segment loop
     const bool ring = !kStamp && lay->ring_segs;
     if (lay->reg_chunks == 8)
-        return ring ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8, !kStamp>)
-                    : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8, false>);
-    return ring ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4, !kStamp>)
-                : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4, false>);
+        return ring ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8, !kStamp, kCol16>)
+                    : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 8, false, kCol16>);
+    return ring ? reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4, !kStamp, kCol16>)
+                : reinterpret_cast<const void *>(solve_tiles<T, kStamp, 4, false, kCol16>);
+}
+template <typename T, bool kStamp>
+const void *tiles_kernel(const sptrsv::Layout *lay) {
+    return lay->col16 ? tiles_kernel_of<T, kStamp, true>(lay) : tiles_kernel_of<T, kStamp, false>(lay);
 }
 
 template <typename T, bool kStamp = false>
@@ -960,16 +982,19 @@ extern "C" int sptrsv_device_limits(int *cus, int *max_waves_per_cu) {
     e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return (int)e;
     // every instance a plan may launch must be co-resident at this count
-    const void *inst[] = {reinterpret_cast<const void *>(solve_tiles<double, false, 4, false>),
-                          reinterpret_cast<const void *>(solve_tiles<double, false, 8, false>),
-                          reinterpret_cast<const void *>(solve_tiles<double, false, 4, true>),
-                          reinterpret_cast<const void *>(solve_tiles<double, false, 8, true>),
-                          reinterpret_cast<const void *>(solve_tiles<float, false, 4, false>),
-                          reinterpret_cast<const void *>(solve_tiles<float, false, 8, false>),
-                          reinterpret_cast<const void *>(solve_tiles<float, false, 4, true>),
-                          reinterpret_cast<const void *>(solve_tiles<float, false, 8, true>),
-                          reinterpret_cast<const void *>(solve_tiles<double, true, 4, false>),
-                          reinterpret_cast<const void *>(solve_tiles<double, true, 8, false>)};
+#define SPTRSV_INSTANCES(C)                                                     \
+    reinterpret_cast<const void *>(solve_tiles<double, false, 4, false, C>),    \
+        reinterpret_cast<const void *>(solve_tiles<double, false, 8, false, C>), \
+        reinterpret_cast<const void *>(solve_tiles<double, false, 4, true, C>),  \
+        reinterpret_cast<const void *>(solve_tiles<double, false, 8, true, C>),  \
+        reinterpret_cast<const void *>(solve_tiles<float, false, 4, false, C>),  \
+        reinterpret_cast<const void *>(solve_tiles<float, false, 8, false, C>),  \
+        reinterpret_cast<const void *>(solve_tiles<float, false, 4, true, C>),   \
+        reinterpret_cast<const void *>(solve_tiles<float, false, 8, true, C>),   \
+        reinterpret_cast<const void *>(solve_tiles<double, true, 4, false, C>),  \
+        reinterpret_cast<const void *>(solve_tiles<double, true, 8, false, C>)
+    const void *inst[] = {SPTRSV_INSTANCES(false), SPTRSV_INSTANCES(true)};
+#undef SPTRSV_INSTANCES
     int most = sptrsv::kMaxWavesPerCU;
     for (const void *k : inst) {
         int b = 0;

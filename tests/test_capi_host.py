@@ -74,7 +74,9 @@ def compare_with_oracle(sp, s, pol):
     assert info["flops_rw"] == oracle.flops(o["lp"][0], o["m"][0])
     assert info["bytes"] == 12 * s.nnz + 24 * s.n
     extra = {0: 0, 1: 16 * s.n, 2: 24 * s.n}[info["rhs_mode"]]
-    assert info["bytes_rw"] == 12 * (info["nnz_rw"] + info["nnz_rhs"]) + 24 * s.n + extra
+    assert info["bytes_rw"] == 12 * (info["nnz_rw"] + info["nnz_rhs"]) + 24 * s.n + extra - 2 * info["compact_terms"]
+    # compact columns: every wide-tile term (the off-diagonal entries not in segments) at 16 bits
+    assert info["compact_terms"] == 0 or info["compact_cols"] == 1
     assert info["nnz_rhs"] == (0 if info["nnz_m"] == 0 else info["nnz_rhs"])
     return plan, o
 
@@ -407,7 +409,7 @@ def test_fp32_plan_keeps_the_schedule(sp):
     n = i64["n"]
     assert i32["bytes"] == 8 * i32["nnz"] + 16 * n
     extra = {0: 0, 1: 8 * n, 2: 16 * n}[i32["rhs_mode"]]
-    assert i32["bytes_rw"] == 8 * (i32["nnz_rw"] + i32["nnz_rhs"]) + 16 * n + extra
+    assert i32["bytes_rw"] == 8 * (i32["nnz_rw"] + i32["nnz_rhs"]) + 16 * n + extra - 2 * i32["compact_terms"]
     assert i64["bytes"] == 12 * i64["nnz"] + 24 * n
     assert np.array_equal(p64.levels(1), p32.levels(1))
     for a, b in zip(p64.export()[0] + p64.export()[1], p32.export()[0] + p32.export()[1]):

@@ -258,3 +258,38 @@ def test_chain_waves_sweep_bitwise(torch, sp, make, pol):
             first = got
         assert np.array_equal(got, first), cw
     plan.close()
+
+
+@pytest.mark.parametrize("make,pol,tpl", [
+    (lambda: wl.banded(60000, 200, 8, 24, seed=2), {"max_width": 10**9, "max_depth": 64, "max_fill": 40.0}, 8),
+    (lambda: wl.banded(20000, 200, 8, 24, seed=7), {"max_width": 10**9, "max_depth": 512, "max_fill": 140.0}, 4),
+    (lambda: wl.stencil2d(150, seed=5), {"max_width": 10**9, "max_depth": 4, "max_fill": 12.0}, 2),
+    (lambda: wl.random_lower(3000, 0.01, seed=9), {"max_width": 10**9, "max_depth": 8, "max_fill": 12.0}, 4),
+], ids=["banded-64", "banded-512", "stencil2d", "random"])
+def test_compact_columns_bitwise(torch, sp, monkeypatch, make, pol, tpl):
+    """Wide tiles that store each column as a 16-bit distance back from the
+    tile's first slot give the same bits as 32-bit columns, in the plain and
+    in the instrumented solve, and the oracle's solution to the gate."""
+    s = make()
+    ref = oracle.solve(s.row_ptr, s.col_idx, s.val, s.b)
+    b = torch.from_numpy(s.b).cuda()
+    got = {}
+    for env in ("", "0"):
+        monkeypatch.setenv("SPTRSV_COMPACT_COLS", env)
+        plan = sp.Plan(s.row_ptr, s.col_idx, s.val).rewrite("threshold", **pol).set_tiling(tpl).upload()
+        info = plan.info()
+        assert info["compact_cols"] == (0 if env == "0" else 1), (env, info["compact_cols"])
+        x = torch.full_like(b, float("nan"))
+        plan.solve(b, x)
+        assert plan.check() == 0
+        xs = torch.full_like(b, float("nan"))
+        stamps = torch.empty(info["tiles"] + info["seg_tiles"] + 1, dtype=torch.int64, device="cuda")
+        plan.solve_stamped(b, xs, stamps)
+        assert plan.check() == 0
+        got[env] = (x.cpu().numpy(), xs.cpu().numpy())
+        print(s.name, "compact" if info["compact_cols"] else "32-bit", info["compact_terms"],
+              relerr(got[env][0], ref), flush=True)
+        assert relerr(got[env][0], ref) <= TOL
+        assert np.array_equal(got[env][0], got[env][1])
+        plan.close()
+    assert np.array_equal(got[""][0], got["0"][0])
