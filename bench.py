@@ -112,12 +112,20 @@ PROFILE = os.path.join(ROOT, "profiles", "solve_tiles_large.md")
 
 def kernel_sources_hash() -> str:
     """Hash of what fixes the solve's memory traffic on the large workload:
-    the built library (kernels and the host passes that lay out the device
-    image; builds are deterministic) and the tuned policies and tilings."""
+    the sources of the kernels and of the host passes that lay out the device
+    image, the public header, the build script (its flags) and the tuned
+    policies and tilings.  Sources rather than the built library, whose bytes
+    also depend on the directory it was built in."""
+    import glob
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2103_11445_amd", "libsptrsv.so"), "rb") as fh:
-        h.update(fh.read())
+    pkg = os.path.join(ROOT, "paper_2103_11445_amd")
+    files = sorted(glob.glob(os.path.join(pkg, "csrc", "*")))
+    files += [os.path.join(ROOT, "include", "sptrsv.h"), os.path.join(pkg, "build.py")]
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     h.update(json.dumps({n: [CANDIDATES[TUNED[n]], TUNED_TILING[n], TUNED_WAVES[n], TUNED_CHAIN[n],
                              TUNED_QUEUES[n]] for n in LARGE}, sort_keys=True).encode())
     return h.hexdigest()
