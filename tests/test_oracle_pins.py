@@ -475,3 +475,84 @@ def test_levelset_solve_matches_serial(make, pol):
     for threads in (1, 4):
         x = oracle.solve_levelset(p["sched_ptr"], p["sched_rows"], p["lp"], p["m"], s.b, threads=threads)
         assert np.array_equal(x, ref), threads
+
+
+# ------------------------------------- merging repeated terms (Fig. 3) --
+
+def _unmerged_terms(rp, ci, level, a, i):
+    """Row i rewritten against a stage starting at level a *without*
+    merging: every in-stage dependency replaced by its original equation,
+    recursively, each path kept as a term of its own.  Returns the lists of
+    x-term and b-term columns, one entry per path (brute force)."""
+    xs, bs = [], []
+    for q in range(rp[i], rp[i + 1] - 1):
+        j = int(ci[q])
+        if level[j] < a:
+            xs.append(j)
+        else:
+            bs.append(j)
+            x2, b2 = _unmerged_terms(rp, ci, level, a, j)
+            xs += x2
+            bs += b2
+    return xs, bs
+
+
+def _stage_start(level, stage_of_level, i):
+    lv = level[i]
+    a = lv
+    while a > 0 and stage_of_level[a - 1] == stage_of_level[lv]:
+        a -= 1
+    return a
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_rearrangement_merges_repeated_terms(seed):
+    """Fig. 3: after substitution the equation is rearranged so that each x
+    and b appears once.  Against the unmerged expansion (one term per path,
+    computed by brute force): the plan's x-terms and b-terms are exactly the
+    distinct columns the paths reach, and its FLOPs never exceed the
+    unmerged count."""
+    rng = np.random.default_rng(seed)
+    s = wl.random_lower(10, rng.uniform(0.2, 0.6), seed=seed)
+    rp, ci = s.row_ptr, s.col_idx
+    level, nlev = oracle.levels(rp, ci)
+    mask = (rng.random(nlev) < 0.7).astype(np.uint8)
+    o = oracle.plan(rp, ci, s.val, {"kind": "explicit", "absorb": mask, "max_entries": 2**40})
+    (lpp, lpc, _), (mp, mc, _) = o["lp"], o["m"]
+    unmerged = 0
+    for i in range(s.n):
+        a = _stage_start(level, o["stage_of_level"], i)
+        if level[i] == a:
+            xs, bs = [int(c) for c in ci[rp[i]:rp[i + 1] - 1]], []
+        else:
+            xs, bs = _unmerged_terms(rp, ci, level, a, i)
+        assert sorted(set(xs)) == [int(c) for c in lpc[lpp[i]:lpp[i + 1] - 1]], i
+        assert sorted(set(bs)) == [int(c) for c in mc[mp[i]:mp[i + 1]]], i
+        unmerged += 2 * (len(xs) + len(bs)) + 1
+    assert oracle.flops(lpp, mp) <= unmerged
+
+
+def test_rearrangement_saving_on_a_diamond_and_none_on_a_chain():
+    """Row 3 reaches row 0 through rows 1 and 2 (a diamond), all in one stage:
+    merged, b_0 appears once instead of twice, a saving of one multiply-add
+    (2 FLOPs).  On a chain every column is reached by one path: nothing to
+    merge."""
+    diamond = wl.from_pairs(4, [(1, 0), (2, 0), (3, 1), (3, 2)], seed=1)
+    lv, nlev = oracle.levels(diamond.row_ptr, diamond.col_idx)
+    assert list(lv) == [0, 1, 1, 2]
+    o = oracle.plan(diamond.row_ptr, diamond.col_idx, diamond.val,
+                    {"kind": "explicit", "absorb": np.array([0, 1, 1], np.uint8), "max_entries": 2**40})
+    xs, bs = _unmerged_terms(diamond.row_ptr, diamond.col_idx, lv, 0, 3)
+    assert sorted(xs) == [] and sorted(bs) == [0, 0, 1, 2]
+    (lpp, _, _), (mp, mc, _) = o["lp"], o["m"]
+    assert list(mc[mp[3]:mp[4]]) == [0, 1, 2]
+    # rows 1, 2 hold b_0 (3 FLOPs each); row 3 merged holds b_0, b_1, b_2 (7),
+    # unmerged four b-terms (9)
+    assert oracle.flops(lpp, mp) == 1 + 3 + 3 + 7 and 1 + 3 + 3 + 9 - oracle.flops(lpp, mp) == 2
+    chain = wl.bidiagonal(6, seed=2)
+    lv, nlev = oracle.levels(chain.row_ptr, chain.col_idx)
+    o = oracle.plan(chain.row_ptr, chain.col_idx, chain.val,
+                    {"kind": "explicit", "absorb": np.ones(nlev, np.uint8), "max_entries": 2**40})
+    for i in range(6):
+        xs, bs = _unmerged_terms(chain.row_ptr, chain.col_idx, lv, 0, i)
+        assert len(bs) == len(set(bs)) and len(xs) == 0
