@@ -544,12 +544,21 @@ template <typename T, bool kStamp, bool kRingOnly>
 __device__ void run_segment(const SolveArgs<T> &a, const int4 d, int lane, T *ring) {
     const long long first = d.x, count = d.y, last = first + count - 1;
     SegSlot<T> S[kDepth];
+    // Prologue in the steady state's order (the first half's loads, their
+    // gathers, then the second half's loads), so that as many loads follow
+    // each gather here as in the loop.  The wait counts the compiler places
+    // at the loop head cover both ways in; with the gathers issued last, a
+    // full memory round trip would be waited out once per kDepth tiles.
 #pragma unroll
-    for (int k = 0; k < kDepth; ++k) seg_load(a, min(first + k, last), lane, S[k]);
+    for (int k = 0; k < kDepth / 2; ++k) seg_load(a, min(first + k, last), lane, S[k]);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < kDepth / 2; ++k) seg_gather<T, kRingOnly>(a, S[k]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = kDepth / 2; k < kDepth; ++k) seg_load(a, min(first + k, last), lane, S[k]);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     for (long long base = 0; base < count; base += kDepth) {
