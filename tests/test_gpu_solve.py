@@ -293,3 +293,56 @@ def test_compact_columns_bitwise(torch, sp, monkeypatch, make, pol, tpl):
         assert np.array_equal(got[env][0], got[env][1])
         plan.close()
     assert np.array_equal(got[""][0], got["0"][0])
+
+
+def _csr_from_rows(rows):
+    """CSR (diagonal last in each row) from a list of [(col, val), ...]."""
+    ptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([c for r in rows for c, _ in r], dtype=np.int32)
+    val = np.array([v for r in rows for _, v in r], dtype=np.float64)
+    return ptr, col, val
+
+
+def test_row_arithmetic_bits_match_ieee(torch, sp):
+    """A row ends with x_i = (b_i + sum_k -L_ik x_k) / L_ii.  Where the sum's
+    order is fixed, the kernel's result must carry the bits of the same
+    operations done one by one in IEEE FP64: a diagonal system (wide tiles,
+    one ragged; x_i = (b_i + 0) / d_i), with signed zeros, subnormals,
+    overflow and extreme diagonals, and a bidiagonal chain run as ring-only
+    segments (x_i = (b_i + RN(-l_i x_{i-1})) / d_i)."""
+    rng = np.random.default_rng(17)
+    n = 100_003
+    d = rng.uniform(0.5, 2.0, n) * np.exp2(rng.integers(-40, 41, n)) * rng.choice([-1.0, 1.0], n)
+    b = rng.uniform(0.5, 2.0, n) * np.exp2(rng.integers(-40, 41, n)) * rng.choice([-1.0, 1.0], n)
+    edge = [(0.0, 3.0), (-0.0, 3.0), (1e-310, 1.5), (-4e-320, 0.75), (1e308, 1e-10), (3.0, 1e-300),
+            (3.0, 1e300), (-2.5, 7e-145), (2.5, 5e144), (1.0, 3.0), (-7.0, 3.0)]
+    for k, (bv, dv) in enumerate(edge):
+        b[1000 * k + 7], d[1000 * k + 7] = bv, dv
+    ptr, col, val = _csr_from_rows([[(i, d[i])] for i in range(n)])
+    plan = sp.Plan(ptr, col, val).upload()
+    x = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    with np.errstate(over="ignore"):
+        want = (b + 0.0) / d
+    plan.solve(torch.from_numpy(b).cuda(), x)
+    got = x.cpu().numpy()
+    assert plan.check() == 0
+    assert np.array_equal(got.view(np.int64), want.view(np.int64))
+
+    m = 6_000
+    dd = rng.uniform(0.5, 2.0, m) * rng.choice([-1.0, 1.0], m)
+    ll = rng.uniform(-1.0, 1.0, m)
+    bb = rng.uniform(-1.0, 1.0, m)
+    rows = [[(0, dd[0])]] + [[(i - 1, ll[i]), (i, dd[i])] for i in range(1, m)]
+    ptr, col, val = _csr_from_rows(rows)
+    plan = sp.Plan(ptr, col, val).upload()
+    assert plan.info()["seg_tiles"] > 0
+    want = np.empty(m)
+    want[0] = (bb[0] + 0.0) / dd[0]
+    for i in range(1, m):
+        want[i] = (bb[i] + (-ll[i]) * want[i - 1]) / dd[i]
+    x = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.solve(torch.from_numpy(bb).cuda(), x)
+    got = x.cpu().numpy()
+    assert plan.check() == 0
+    assert np.array_equal(got.view(np.int64), want.view(np.int64))
